@@ -1,0 +1,110 @@
+/*
+ * psd.h -- phase-space-element density deposition on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libpsd.so.  Plain C types only; a HIP stream is passed as void*
+ * (a hipStream_t, NULL = the default stream).
+ *
+ * The method (Kaehler, "Massively Parallel Computation of Accurate Densities
+ * for N-body Dark Matter Simulations using the Phase-Space-Element Method"):
+ * tracers sit on a Lagrangian grid of fixed connectivity and equal mass
+ * (Section 2); each hexahedral cell of that grid is split into 6 tetrahedra
+ * (Section 2; here the Freudenthal split along the 000-111 diagonal); the
+ * density is Eq. (1), rho(x) = m sum_i 1/V_i(x), and its average over a
+ * cubical cell C is M_C / h^3 with M_C = sum_T m |T cap C| / |T|, where
+ * |T cap C| is the exact intersection volume (Section 6.3).
+ *
+ * Conventions shared by every call:
+ *   - Positions: float32 [np0][np1][np2][3], C order (x index slowest), in a
+ *     periodic cube of side `box`; any finite value is accepted and wrapped.
+ *     Each cube's corners are unwrapped to the minimum image of corner 000.
+ *   - Mass per tetrahedron m = total_mass / (6 np0 np1 np2).
+ *   - Grids: [nc0][nc1][nc2], C order, cell (a,b,c) covers
+ *     [a,a+1) x [b,b+1) x [c,c+1) in units of h_k = box / nc_k.
+ *   - All data pointers are DEVICE pointers unless marked (host).  The
+ *     caller allocates every buffer, including the workspace; calls never
+ *     allocate device memory, keep no state between calls and never free
+ *     caller memory.
+ *   - Calls enqueue work on `stream` and return without synchronising,
+ *     except where stated.  On error nothing is enqueued and outputs are
+ *     unspecified.  No C++ exception crosses this boundary.
+ */
+#ifndef PSD_H
+#define PSD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PSD_OK = 0,
+    PSD_ERR_ARG = -1,         /* null pointer, non-positive size, bad value   */
+    PSD_ERR_WORKSPACE = -2,   /* workspace smaller than psd_*_workspace_size  */
+    PSD_ERR_CAPACITY = -3,    /* octree node array too small (see below)      */
+    PSD_ERR_NONFINITE = -4,   /* reserved                                      */
+    PSD_ERR_UNSUPPORTED = -5, /* flag combination not supported               */
+    PSD_ERR_HIP = -6          /* a HIP runtime call failed (see detail string) */
+} psd_status;
+
+enum {
+    PSD_OUT_DENSITY = 1u << 0, /* write mass / h^3 instead of cell mass        */
+    PSD_ACCUMULATE = 1u << 1,  /* add into `out` instead of overwriting it     */
+    PSD_PREC_FP64 = 1u << 2,   /* FP64 output grid (`out` is double); with
+                                  PSD_METHOD_CELL also FP64 clipping          */
+    PSD_METHOD_CELL = 1u << 3  /* per-cell exact clip in cell-local FP32
+                                  coordinates (Section 6.1 loop cell by cell);
+                                  default: cumulative FP64 volumes            */
+};
+
+typedef struct {
+    int32_t np[3];     /* Lagrangian grid size (particles per axis), each >= 1 */
+    double box;        /* periodic box side, > 0                              */
+    double total_mass; /* mass of all particles                               */
+} psd_particles;
+
+typedef struct {
+    uint32_t flags;    /* PSD_* flags above                                   */
+    int64_t* stats;    /* optional DEVICE int64[8] counters, added into:
+                          [0] tets, [1] (tet, bbox cell) pairs, [2] exact
+                          clips, [3] non-zero deposits, [4] inverted tets,
+                          [5] zero-volume tets, [6..7] reserved; may be NULL */
+} psd_options;
+
+/* Workspace bytes (host out) needed by psd_deposit_uniform for this problem. */
+psd_status psd_uniform_workspace_size(const psd_particles* p, const int32_t nc[3],
+                                      const psd_options* opt, size_t* bytes);
+
+/*
+ * Cell masses (or densities) of the whole tessellation on a periodic uniform
+ * grid (Section 6.1 deposit loop; Section 6.3 exact intersection).
+ * Default method: for each column (a,b) of a tetrahedron's bounding box, the
+ * volumes of T cap {x<=a+1, y<=b+1} per z-cell (two-plane splitting plus the
+ * exact distribution along z), cell volumes by 2-D differences, all FP64.
+ * PSD_METHOD_CELL: classify each bbox cell and clip the non-trivial ones
+ * exactly, cell-local FP32 (FP64 for distances to the tetrahedron's planes).
+ *   pos       DEVICE float [np0][np1][np2][3]
+ *   p, nc     host; nc[k] >= 1
+ *   out       DEVICE float [nc0][nc1][nc2] (double with PSD_PREC_FP64);
+ *             zeroed first unless PSD_ACCUMULATE
+ *   mass_sum  DEVICE double[1] or NULL: set (or, with PSD_ACCUMULATE, added)
+ *             to the FP64 sum of every mass deposited by this call
+ *   opt       host, may be NULL (flags 0)
+ *   ws        DEVICE workspace of ws_bytes >= psd_uniform_workspace_size
+ * Errors: PSD_ERR_ARG, PSD_ERR_WORKSPACE, PSD_ERR_HIP.  Asynchronous.
+ */
+psd_status psd_deposit_uniform(const float* pos, const psd_particles* p, const int32_t nc[3],
+                               void* out, double* mass_sum, const psd_options* opt, void* ws,
+                               size_t ws_bytes, void* stream);
+
+/* Human-readable name of a status code (static string). */
+const char* psd_status_string(psd_status s);
+
+/* Detail of the last error raised on the calling host thread (thread-local). */
+const char* psd_last_error_detail(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,440 @@
+// psd_cumulative.hip -- exact deposit by cumulative (inclusion-exclusion) volumes.
+//
+// Same result as the per-cell clip (Section 6.3 intersection volumes summed
+// as in Section 6.1), organised for a SIMD machine:
+//
+//   D(a,b,l) = |T cap {x <= a+1} cap {y <= b+1} cap {l <= z <= l+1}| / |T|
+//
+// for every vertex column (a,b) of the bounding box (coordinates relative to
+// its origin).  Each column needs T split by only two half-spaces -- with the
+// inside-mask table of Section 6.3, at most 3 x 3 pieces -- and each piece's
+// share of every z-cell follows from the exact distribution of z over a
+// tetrahedron (the fraction of a tetrahedron below a plane, evaluated from
+// its four vertex distances), which plays the role of the paper's
+// subtraction along the last axis.  A cell's volume is then the 2-D
+// difference D(i,j) - D(i-1,j) - D(i,j-1) + D(i-1,j-1).  Differences cancel,
+// so everything is FP64 (full VALU rate on gfx950).
+//
+// One wavefront per workgroup.  Lanes build 64 tetrahedra into LDS; small
+// ones are batched so their D arrays share an LDS buffer; larger ones are
+// tiled.  Phase 1 spreads (tet, column) pairs over lanes, phase 2 spreads
+// (tet, cell) pairs and scatters the non-zero cell masses with global atomics.
+#include "psd_internal.h"
+
+namespace psd {
+
+namespace {
+
+constexpr int kCap = 1024;  // FP64 entries of the D buffer
+
+struct CTet {
+    double vr[4][3];  // vertices relative to the bbox origin (cell units), exact
+    int lo[3];        // bbox origin wrapped into [0, nc)
+    int ext[3];       // bbox extent in cells
+    int ncell;        // ext0 * ext1 * ext2 (0: nothing to do)
+    int ncol;         // ext0 * ext1
+};
+
+// A tile of one tetrahedron's cells: x in [a0, a0+ta), y in [b0, b0+tb),
+// z in [l0, l0+tl).  Its D buffer covers columns a in [a0-ha, a0+ta),
+// b in [b0-hb, b0+tb) (ha, hb = 1 when a lower neighbour column exists).
+struct Tile {
+    int a0, ta, b0, tb, l0, tl;
+    int ha, hb;
+    int doff;  // offset in the D buffer
+};
+
+// Tile shape for a tetrahedron whose D array exceeds the buffer:
+// (ta+1)*(tb+1)*tl <= kCap with ta, tb >= 1.
+__device__ __forceinline__ void tile_shape(const CTet& S, int& ta, int& tb, int& tl, int& ntiles)
+{
+    tl = min(S.ext[2], kCap / 4);
+    tb = min(S.ext[1], kCap / (2 * tl) - 1);
+    ta = min(S.ext[0], kCap / (tl * (tb + 1)) - 1);
+    ntiles = ((S.ext[0] + ta - 1) / ta) * ((S.ext[1] + tb - 1) / tb) * ((S.ext[2] + tl - 1) / tl);
+}
+
+__device__ __forceinline__ int tile_cols(const Tile& t) { return (t.ta + t.ha) * (t.tb + t.hb); }
+__device__ __forceinline__ int tile_dsize(const Tile& t) { return tile_cols(t) * t.tl; }
+__device__ __forceinline__ int tile_cells(const Tile& t) { return t.ta * t.tb * t.tl; }
+
+__device__ __forceinline__ int wrap_add(int base, int off, int n)
+{
+    int x = base + off;
+    return x >= n ? x - n : x;
+}
+
+// Fraction of the tetrahedron with vertex heights z[] lying at z <= k.
+__device__ __forceinline__ double below(const double z[4], double k)
+{
+    double d[4] = {k - z[0], k - z[1], k - z[2], k - z[3]};
+    Split<double> s;
+    split_plane(d, s);
+    return s.f0 + s.f1 + s.f2;
+}
+
+// Adds frac * (share of each z-cell of the tile) for one piece.
+__device__ __forceinline__ void spread_z(const double z[4], double frac, const Tile& t,
+                                         double* Dcol)
+{
+    const double zmin = fmin(fmin(z[0], z[1]), fmin(z[2], z[3]));
+    const double zmax = fmax(fmax(z[0], z[1]), fmax(z[2], z[3]));
+    const int lfirst = (int)floor(zmin);
+    const int lA = max(lfirst, t.l0);
+    const int lB = min((int)floor(zmax), t.l0 + t.tl - 1);
+    if (lA > lB) return;
+    double Fprev = (lA <= lfirst) ? 0.0 : below(z, (double)lA);
+    for (int l = lA; l <= lB; ++l) {
+        const double kn = (double)(l + 1);
+        const double Fnext = (kn >= zmax) ? 1.0 : below(z, kn);
+        Dcol[l - t.l0] += frac * (Fnext - Fprev);
+        Fprev = Fnext;
+    }
+}
+
+// D column (a,b) of one tile: T cut by x <= a+1 and y <= b+1.
+__device__ __forceinline__ void column(const CTet& S, int a, int b, const Tile& t, double* Dcol)
+{
+    for (int l = 0; l < t.tl; ++l) Dcol[l] = 0.0;
+    const bool cx = a + 1 < S.ext[0];
+    const bool cy = b + 1 < S.ext[1];
+    const double X = (double)(a + 1), Y = (double)(b + 1);
+    double v[4][3];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[q][c] = S.vr[q][c];
+
+    // level 1: x <= X (inside when X - x >= 0)
+    double dx[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dx[q] = cx ? X - v[q][0] : 1.0;
+    Split<double> s1;
+    split_plane(dx, s1);
+    if (s1.nin == 0) return;
+    // permuted vertices' (y, z)
+    double P1[4][2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        P1[0][c] = sel4(v[0][c + 1], v[1][c + 1], v[2][c + 1], v[3][c + 1], s1.ia);
+        P1[1][c] = sel4(v[0][c + 1], v[1][c + 1], v[2][c + 1], v[3][c + 1], s1.ib);
+        P1[2][c] = sel4(v[0][c + 1], v[1][c + 1], v[2][c + 1], v[3][c + 1], s1.ic);
+        P1[3][c] = sel4(v[0][c + 1], v[1][c + 1], v[2][c + 1], v[3][c + 1], s1.id);
+    }
+    const bool a1 = s1.nin == 1, a2 = s1.nin == 2, a3 = s1.nin == 3, a4 = s1.nin == 4;
+    double U0[2], U1[2], U2[2], W0[2], W1[2], W2[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const double va = P1[0][c], vb = P1[1][c], vc = P1[2][c], vd = P1[3][c];
+        const double in1 = a3 ? vb : va, in2 = a1 ? va : (a2 ? vb : vc);
+        const double out0 = a1 ? vb : (a2 ? vc : vd), out1 = a1 ? vc : vd, out2 = a2 ? vc : vd;
+        const double c0 = va + s1.t0 * (out0 - va);
+        const double c1 = in1 + s1.t1 * (out1 - in1);
+        const double c2 = in2 + s1.t2 * (out2 - in2);
+        const double c3 = vb + s1.t3 * (vd - vb);
+        U0[c] = va;
+        U1[c] = (a3 || a4) ? vb : c0;
+        U2[c] = (a3 || a4) ? vc : c1;
+        W0[c] = a2 ? vb : c0;
+        W1[c] = a2 ? c2 : c1;
+        W2[c] = a4 ? vd : (a2 ? c3 : c2);
+    }
+    const int n1 = (a2 || a3) ? 3 : 1;
+    for (int j = 0; j < n1; ++j) {
+        double cv[4][2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            cv[0][c] = U0[c];
+            cv[1][c] = j == 2 ? W0[c] : U1[c];
+            cv[2][c] = j == 0 ? U2[c] : W1[c];
+            cv[3][c] = W2[c];
+        }
+        const double f1 = j == 0 ? s1.f0 : (j == 1 ? s1.f1 : s1.f2);
+        // level 2: y <= Y
+        double dy[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dy[q] = cy ? Y - cv[q][0] : 1.0;
+        Split<double> s2;
+        split_plane(dy, s2);
+        if (s2.nin == 0) continue;
+        double za = sel4(cv[0][1], cv[1][1], cv[2][1], cv[3][1], s2.ia);
+        double zb = sel4(cv[0][1], cv[1][1], cv[2][1], cv[3][1], s2.ib);
+        double zc = sel4(cv[0][1], cv[1][1], cv[2][1], cv[3][1], s2.ic);
+        double zd = sel4(cv[0][1], cv[1][1], cv[2][1], cv[3][1], s2.id);
+        const bool b1 = s2.nin == 1, b2 = s2.nin == 2, b3 = s2.nin == 3, b4 = s2.nin == 4;
+        const double in1 = b3 ? zb : za, in2 = b1 ? za : (b2 ? zb : zc);
+        const double out0 = b1 ? zb : (b2 ? zc : zd), out1 = b1 ? zc : zd, out2 = b2 ? zc : zd;
+        const double c0 = za + s2.t0 * (out0 - za);
+        const double c1 = in1 + s2.t1 * (out1 - in1);
+        const double c2 = in2 + s2.t2 * (out2 - in2);
+        const double c3 = zb + s2.t3 * (zd - zb);
+        const double u0 = za, u1 = (b3 || b4) ? zb : c0, u2 = (b3 || b4) ? zc : c1;
+        const double w0 = b2 ? zb : c0, w1 = b2 ? c2 : c1, w2 = b4 ? zd : (b2 ? c3 : c2);
+        const int n2 = (b2 || b3) ? 3 : 1;
+        for (int k = 0; k < n2; ++k) {
+            const double z[4] = {u0, k == 2 ? w0 : u1, k == 0 ? u2 : w1, w2};
+            const double f2 = k == 0 ? s2.f0 : (k == 1 ? s2.f1 : s2.f2);
+            spread_z(z, f1 * f2, t, Dcol);
+        }
+    }
+}
+
+template <typename OutT>
+__global__ __launch_bounds__(kWave) void deposit_cumulative_kernel(UniformArgs P)
+{
+    __shared__ CTet slots[kWave];
+    __shared__ double Dbuf[kCap];
+    __shared__ Tile tiles[kWave];
+    __shared__ int t_slot[kWave];
+    __shared__ int64_t s_incl[kWave];
+
+    OutT* out = reinterpret_cast<OutT*>(P.out);
+    const int lane = threadIdx.x;
+    const double sc[3] = {P.scale[0], P.scale[1], P.scale[2]};
+    double macc = 0.0;
+    unsigned long long n_tet = 0, n_pair = 0, n_col = 0, n_nz = 0, n_inv = 0, n_deg = 0;
+
+    for (int64_t chunk = blockIdx.x; chunk * kWave < P.ntet; chunk += gridDim.x) {
+        const int64_t tid = chunk * kWave + lane;
+        int ncell = 0;
+        if (tid < P.ntet) {
+            const int64_t cube = tid / 6;
+            const int p = (int)(tid - cube * 6);
+            const int64_t kk = cube % P.np[2];
+            const int64_t jj = (cube / P.np[2]) % P.np[1];
+            const int64_t ii = cube / ((int64_t)P.np[1] * P.np[2]);
+            Tet64 T;
+            make_tet(P.pos, P.np[0], P.np[1], P.np[2], sc, P.nc, ii, jj, kk, p, T);
+            ++n_tet;
+            if ((double)kuhn_sign(p) * T.D < 0.0) ++n_inv;
+            const bool finite_tet = isfinite(T.D) && isfinite(T.l3);
+            if (!finite_tet) {
+                // non-finite input cannot be placed; the tetrahedron is dropped
+            } else if (fabs(T.D) <= 1e-12 * T.l3) {
+                // zero-volume tetrahedron: all mass to the centroid's cell
+                ++n_deg;
+                ++n_nz;
+                int g[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const double x = 0.25 * (T.v[0][c] + T.v[1][c] + T.v[2][c] + T.v[3][c]);
+                    const double fl = floor(x);
+                    const double n = (double)P.nc[c];
+                    g[c] = (int)(fl - n * floor(fl / n));
+                }
+                const int64_t idx = ((int64_t)g[0] * P.nc[1] + g[1]) * P.nc[2] + g[2];
+                atomicAdd(out + idx, (OutT)(P.m * P.out_scale));
+                macc += P.m;
+            } else {
+                CTet& S = slots[lane];
+                bool ok = true;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const double mn = fmin(fmin(T.v[0][c], T.v[1][c]), fmin(T.v[2][c], T.v[3][c]));
+                    const double mx = fmax(fmax(T.v[0][c], T.v[1][c]), fmax(T.v[2][c], T.v[3][c]));
+                    const double lo = floor(mn);
+                    const int e = (int)(floor(mx) - lo) + 1;
+                    ok = ok && e >= 1 && e <= P.nc[c] + 1;
+                    const double n = (double)P.nc[c];
+                    S.lo[c] = (int)(lo - n * floor(lo / n));
+                    S.ext[c] = e;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) S.vr[q][c] = T.v[q][c] - lo;
+                }
+                ncell = ok ? S.ext[0] * S.ext[1] * S.ext[2] : 0;
+                S.ncell = ncell;
+                S.ncol = ok ? S.ext[0] * S.ext[1] : 0;
+                if (ncell == 1) {
+                    // the tetrahedron lies inside one cell
+                    ++n_pair;
+                    ++n_nz;
+                    const int64_t idx = ((int64_t)S.lo[0] * P.nc[1] + S.lo[1]) * P.nc[2] + S.lo[2];
+                    atomicAdd(out + idx, (OutT)(P.m * P.out_scale));
+                    macc += P.m;
+                    ncell = 0;
+                    S.ncell = 0;
+                }
+            }
+        }
+        if (tid >= P.ntet || ncell == 0) {
+            // mark the slot empty (the record may hold a stale tetrahedron)
+            slots[lane].ncell = 0;
+        }
+        __syncthreads();
+
+        // Walk the chunk's tetrahedra in tile batches that fit the D buffer.
+        int cur = 0;       // next slot to start
+        int cur_tile = 0;  // for a tiled tetrahedron, linear index of its next tile
+        while (cur < kWave) {
+            // Wave-uniform planning (every lane computes the same list).
+            int nt = 0, used = 0;
+            while (cur < kWave && nt < kWave) {
+                const CTet& S = slots[cur];
+                if (S.ncell == 0) {
+                    ++cur;
+                    cur_tile = 0;
+                    continue;
+                }
+                Tile t;
+                int ntiles = 1;
+                if (S.ncell <= kCap) {
+                    t.a0 = 0; t.ta = S.ext[0]; t.b0 = 0; t.tb = S.ext[1];
+                    t.l0 = 0; t.tl = S.ext[2]; t.ha = 0; t.hb = 0;
+                } else {
+                    int ta, tb, tl;
+                    tile_shape(S, ta, tb, tl, ntiles);
+                    const int nx = (S.ext[0] + ta - 1) / ta, ny = (S.ext[1] + tb - 1) / tb;
+                    const int ix = cur_tile % nx, iy = (cur_tile / nx) % ny, iz = cur_tile / (nx * ny);
+                    t.a0 = ix * ta; t.ta = min(ta, S.ext[0] - t.a0);
+                    t.b0 = iy * tb; t.tb = min(tb, S.ext[1] - t.b0);
+                    t.l0 = iz * tl; t.tl = min(tl, S.ext[2] - t.l0);
+                    t.ha = t.a0 > 0 ? 1 : 0;
+                    t.hb = t.b0 > 0 ? 1 : 0;
+                }
+                const int ds = tile_dsize(t);
+                if (used + ds > kCap) break;  // buffer full: run this batch first
+                t.doff = used;
+                used += ds;
+                if (lane == 0) {
+                    tiles[nt] = t;
+                    t_slot[nt] = cur;
+                }
+                ++nt;
+                if (++cur_tile >= ntiles) {
+                    ++cur;
+                    cur_tile = 0;
+                }
+            }
+            __syncthreads();
+            if (nt == 0) continue;
+
+            // Phase 1: (tile, column) pairs over lanes.
+            {
+                int64_t c = lane < nt ? tile_cols(tiles[lane]) : 0;
+                int64_t incl = c;
+#pragma unroll
+                for (int off = 1; off < kWave; off <<= 1) {
+                    const int64_t y = __shfl_up(incl, off, kWave);
+                    if (lane >= off) incl += y;
+                }
+                s_incl[lane] = incl;
+                __syncthreads();
+                const int64_t total = __shfl(incl, kWave - 1, kWave);
+                for (int64_t base = 0; base < total; base += kWave) {
+                    const int64_t idx = base + lane;
+                    if (idx < total) {
+                        int lo = 0, hi = nt - 1;
+                        while (lo < hi) {
+                            const int mid = (lo + hi) >> 1;
+                            if (s_incl[mid] > idx) hi = mid;
+                            else lo = mid + 1;
+                        }
+                        const Tile t = tiles[lo];
+                        const CTet& S = slots[t_slot[lo]];
+                        const int r = (int)(idx - (s_incl[lo] - tile_cols(t)));
+                        const int wb = t.tb + t.hb;
+                        const int a = t.a0 - t.ha + r / wb;
+                        const int b = t.b0 - t.hb + r % wb;
+                        column(S, a, b, t, Dbuf + t.doff + r * t.tl);
+                        ++n_col;
+                    }
+                }
+                __syncthreads();
+            }
+            // Phase 2: (tile, cell) pairs over lanes.
+            {
+                int64_t c = lane < nt ? tile_cells(tiles[lane]) : 0;
+                int64_t incl = c;
+#pragma unroll
+                for (int off = 1; off < kWave; off <<= 1) {
+                    const int64_t y = __shfl_up(incl, off, kWave);
+                    if (lane >= off) incl += y;
+                }
+                s_incl[lane] = incl;
+                __syncthreads();
+                const int64_t total = __shfl(incl, kWave - 1, kWave);
+                for (int64_t base = 0; base < total; base += kWave) {
+                    const int64_t idx = base + lane;
+                    if (idx < total) {
+                        int lo = 0, hi = nt - 1;
+                        while (lo < hi) {
+                            const int mid = (lo + hi) >> 1;
+                            if (s_incl[mid] > idx) hi = mid;
+                            else lo = mid + 1;
+                        }
+                        const Tile t = tiles[lo];
+                        const CTet& S = slots[t_slot[lo]];
+                        const int r = (int)(idx - (s_incl[lo] - tile_cells(t)));
+                        // r -> (i, j, l) within the tile, l fastest
+                        const int l = r % t.tl;
+                        const int ij = r / t.tl;
+                        const int j = ij % t.tb;
+                        const int i = ij / t.tb;
+                        const int wb = t.tb + t.hb;
+                        const double* D = Dbuf + t.doff;
+                        // column index of (a, b) = (t.a0 + i, t.b0 + j) in the buffer
+                        const int ca = i + t.ha, cb = j + t.hb;
+                        const double d11 = D[(ca * wb + cb) * t.tl + l];
+                        const bool has_a = (t.a0 + i) > 0, has_b = (t.b0 + j) > 0;
+                        const double d01 = has_a ? D[((ca - 1) * wb + cb) * t.tl + l] : 0.0;
+                        const double d10 = has_b ? D[(ca * wb + cb - 1) * t.tl + l] : 0.0;
+                        const double d00 = (has_a && has_b) ? D[((ca - 1) * wb + cb - 1) * t.tl + l] : 0.0;
+                        const double V = (d11 - d01) - (d10 - d00);
+                        ++n_pair;
+                        // differences of values up to 1 carry ~1e-16 noise: drop it
+                        if (V > 4e-15) {
+                            ++n_nz;
+                            const int gx = wrap_add(S.lo[0], t.a0 + i, P.nc[0]);
+                            const int gy = wrap_add(S.lo[1], t.b0 + j, P.nc[1]);
+                            const int gz = wrap_add(S.lo[2], t.l0 + l, P.nc[2]);
+                            const int64_t gi = ((int64_t)gx * P.nc[1] + gy) * P.nc[2] + gz;
+                            const double mass = P.m * V;
+                            atomicAdd(out + gi, (OutT)(mass * P.out_scale));
+                            macc += mass;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        macc += __shfl_xor(macc, off, kWave);
+        n_tet += __shfl_xor(n_tet, off, kWave);
+        n_pair += __shfl_xor(n_pair, off, kWave);
+        n_col += __shfl_xor(n_col, off, kWave);
+        n_nz += __shfl_xor(n_nz, off, kWave);
+        n_inv += __shfl_xor(n_inv, off, kWave);
+        n_deg += __shfl_xor(n_deg, off, kWave);
+    }
+    if (lane == 0) {
+        if (P.mass_sum) atomicAdd(P.mass_sum, macc);
+        if (P.stats) {
+            atomicAdd(P.stats + 0, n_tet);
+            atomicAdd(P.stats + 1, n_pair);
+            atomicAdd(P.stats + 2, n_col);
+            atomicAdd(P.stats + 3, n_nz);
+            atomicAdd(P.stats + 4, n_inv);
+            atomicAdd(P.stats + 5, n_deg);
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_deposit_cumulative(const UniformArgs& P, bool out_fp64, hipStream_t stream)
+{
+    const int64_t nchunk = (P.ntet + kWave - 1) / kWave;
+    int grid = (int)(nchunk < (int64_t)P.grid_limit ? nchunk : (int64_t)P.grid_limit);
+    if (grid < 1) grid = 1;
+    if (out_fp64)
+        hipLaunchKernelGGL(deposit_cumulative_kernel<double>, dim3(grid), dim3(kWave), 0, stream, P);
+    else
+        hipLaunchKernelGGL(deposit_cumulative_kernel<float>, dim3(grid), dim3(kWave), 0, stream, P);
+    return hipGetLastError();
+}
+
+}  // namespace psd

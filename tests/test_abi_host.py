@@ -1,0 +1,81 @@
+"""Host-side checks of the C ABI (no GPU work is launched).
+
+The library must load, export every function declared in include/psd.h, and
+reject bad arguments on the host before touching the device.
+"""
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def psd():
+    import paper_1612_09491_amd as psd
+    if not os.path.exists(psd.LIB_PATH):
+        from paper_1612_09491_amd import build
+        build.build()
+    return psd
+
+
+def _declared_functions():
+    names = []
+    for hdr in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not hdr.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", hdr)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"\b(psd_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported(psd):
+    names = _declared_functions()
+    assert "psd_deposit_uniform" in names and len(names) >= 4
+    L = C.CDLL(psd.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_status_strings(psd):
+    L = psd.lib()
+    assert L.psd_status_string(0) == b"PSD_OK"
+    assert L.psd_status_string(-2) == b"PSD_ERR_WORKSPACE"
+
+
+def test_workspace_size_and_argument_errors(psd):
+    assert psd.uniform_workspace_size((8, 8, 8), 16) > 0
+    with pytest.raises(psd.PsdError) as e:
+        psd.uniform_workspace_size((0, 8, 8), 16)
+    assert e.value.code == psd.PSD_ERR_ARG
+    with pytest.raises(psd.PsdError) as e:
+        psd.uniform_workspace_size((8, 8, 8), (16, 0, 16))
+    assert e.value.code == psd.PSD_ERR_ARG
+    with pytest.raises(psd.PsdError) as e:
+        psd.uniform_workspace_size((8, 8, 8), 16, flags=1 << 20)
+    assert e.value.code == psd.PSD_ERR_UNSUPPORTED
+
+
+def test_deposit_rejects_bad_arguments_before_launch(psd):
+    L = psd.lib()
+    p = psd.Particles()
+    for a in range(3):
+        p.np[a] = 4
+    p.box, p.total_mass = 1.0, 1.0
+    nc = (C.c_int32 * 3)(8, 8, 8)
+    o = psd.Options(0, None)
+    fake = C.c_void_p(0x1000)  # never dereferenced: checks fail first
+    assert L.psd_deposit_uniform(None, C.byref(p), nc, fake, None, C.byref(o), fake, 4096,
+                                 None) == psd.PSD_ERR_ARG
+    assert L.psd_deposit_uniform(fake, C.byref(p), nc, fake, None, C.byref(o), fake, 1,
+                                 None) == psd.PSD_ERR_WORKSPACE
+    assert L.psd_deposit_uniform(fake, C.byref(p), nc, fake, None, C.byref(o), None, 4096,
+                                 None) == psd.PSD_ERR_WORKSPACE
+    p.box = -1.0
+    assert L.psd_deposit_uniform(fake, C.byref(p), nc, fake, None, C.byref(o), fake, 4096,
+                                 None) == psd.PSD_ERR_ARG
+    assert b"particle" in L.psd_last_error_detail()

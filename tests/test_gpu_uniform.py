@@ -1,0 +1,197 @@
+"""GPU parity of psd_deposit_uniform against the FP64 oracle.
+
+Both methods are checked: the default cumulative method (FP64 arithmetic) and
+the per-cell cell-local FP32 clip (PSD_METHOD_CELL).  Tolerances: an FP32
+output grid or FP32 clipping within 1e-5 relative L1 and Linf of the
+oracle's densities; FP64 arithmetic into an FP64 grid within 1e-12.  Integer
+counters (tets, bbox pairs, inverted, zero-volume) must match exactly.
+"""
+
+import functools
+
+import numpy as np
+import pytest
+import torch
+
+from synth import lattice_positions, zeldovich_positions, workload
+
+pytestmark = pytest.mark.gpu
+
+FP32_L1 = 1e-5
+FP32_LINF = 1e-5
+FP64_L1 = 1e-12
+FP64_LINF = 1e-11
+
+
+@pytest.fixture(scope="module")
+def psd():
+    import os
+    import paper_1612_09491_amd as psd
+    if not os.path.exists(psd.LIB_PATH):
+        from paper_1612_09491_amd import build
+        build.build()
+    return psd
+
+
+def _run(psd, pos, nc, flags=0, box=1.0, mass=1.0):
+    dev = torch.device("cuda:0")
+    pt = torch.from_numpy(np.ascontiguousarray(pos)).to(dev)
+    ms = torch.zeros(1, dtype=torch.float64, device=dev)
+    st = torch.zeros(8, dtype=torch.int64, device=dev)
+    out = psd.deposit_uniform(pt, nc, box=box, mass=mass, flags=flags, mass_sum=ms, stats=st)
+    torch.cuda.synchronize()
+    return out.double().cpu().numpy(), float(ms.item()), st.cpu().numpy()
+
+
+def _rel_l1(a, b):
+    return float(np.abs(a - b).sum() / np.abs(b).sum())
+
+
+def _rel_linf(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def _check_stats(st, cnt):
+    assert st[0] == cnt["n_tet"]
+    assert st[1] == cnt["n_pair"]
+    assert st[4] == cnt["n_inverted"]
+    assert st[5] == cnt["n_degenerate"]
+
+
+METHODS = {"cumulative": 0, "cell": 8}  # 8 = PSD_METHOD_CELL
+
+
+@pytest.mark.parametrize("method", list(METHODS))
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
+def test_zel32_g64_fp32(psd, orc, seed, method):
+    pos, p = workload("zel32_g64", seed=seed)
+    ref, cnt = orc.deposit_uniform(pos, p["nc"])
+    got, msum, st = _run(psd, pos, p["nc"], flags=METHODS[method])
+    l1, linf = _rel_l1(got, ref), _rel_linf(got, ref)
+    print(f"seed {seed}: L1 {l1:.3e} Linf {linf:.3e} mass {msum - 1:.3e}")
+    assert l1 <= FP32_L1 and linf <= FP32_LINF
+    assert abs(msum - 1.0) <= 1e-6
+    _check_stats(st, cnt)
+
+
+@pytest.mark.parametrize("method", list(METHODS))
+@pytest.mark.parametrize("seed", [1, 2])
+def test_zel32_g64_fp64(psd, orc, seed, method):
+    pos, p = workload("zel32_g64", seed=seed)
+    ref, cnt = orc.deposit_uniform(pos, p["nc"])
+    got, msum, st = _run(psd, pos, p["nc"], flags=psd.PSD_PREC_FP64 | METHODS[method])
+    assert _rel_l1(got, ref) <= FP64_L1 and _rel_linf(got, ref) <= FP64_LINF
+    assert abs(msum - 1.0) <= 1e-12
+    _check_stats(st, cnt)
+
+
+@pytest.mark.parametrize("method", list(METHODS))
+@pytest.mark.parametrize("nc", [64, 16, 24])
+def test_undisplaced_lattice_is_uniform(psd, nc, method):
+    pos = lattice_positions(32)
+    got, _, st = _run(psd, pos, nc, flags=METHODS[method])
+    assert np.max(np.abs(got * nc ** 3 - 1.0)) <= 1e-5
+    got64, _, _ = _run(psd, pos, nc, flags=psd.PSD_PREC_FP64 | METHODS[method])
+    assert np.max(np.abs(got64 * nc ** 3 - 1.0)) <= 1e-12
+
+
+def _compare(psd, orc, pos, nc, box=1.0, mass=1.0, l1=FP32_L1):
+    ref, cnt = orc.deposit_uniform(pos, nc, box=box, mass=mass)
+    for m in METHODS.values():
+        got, msum, st = _run(psd, pos, nc, box=box, mass=mass, flags=m)
+        assert _rel_l1(got, ref) <= l1, (m, _rel_l1(got, ref))
+        got64, msum64, _ = _run(psd, pos, nc, flags=psd.PSD_PREC_FP64 | m, box=box, mass=mass)
+        assert _rel_l1(got64, ref) <= FP64_L1, (m, _rel_l1(got64, ref))
+        assert abs(msum64 - mass) <= 1e-12 * abs(mass)
+        _check_stats(st, cnt)
+    return got, ref
+
+
+def test_single_particle_grid(psd, orc):
+    pos = np.array([[[[0.3, 0.6, 0.9]]]], dtype=np.float32)
+    got, ref = _compare(psd, orc, pos, 8)
+    assert got[2, 4, 7] == pytest.approx(1.0)
+
+
+def test_single_cell_grid(psd, orc):
+    pos = zeldovich_positions(6, 0.7, seed=41)
+    got, ref = _compare(psd, orc, pos, 1)
+    assert got[0, 0, 0] == pytest.approx(1.0, rel=1e-6)
+
+
+def test_anisotropic_ragged_grids(psd, orc):
+    rng = np.random.default_rng(42)
+    q = np.moveaxis(np.indices((3, 5, 2), dtype=np.float64), 0, -1) / np.array([3, 5, 2])
+    pos = np.mod(q + rng.normal(scale=0.05, size=q.shape), 1.0).astype(np.float32)
+    _compare(psd, orc, pos, (7, 9, 4))
+    pos2 = zeldovich_positions(10, 0.8, seed=43)
+    _compare(psd, orc, pos2, (37, 20, 13))
+
+
+def test_huge_stretched_tets(psd, orc):
+    pos = zeldovich_positions(4, 1.4, seed=44)
+    _compare(psd, orc, pos, 48)
+
+
+def test_flat_tets_go_to_centroid_cell(psd, orc):
+    pos = lattice_positions(8).astype(np.float64)
+    pos[:, :, :, 2] = 0.3
+    got, ref = _compare(psd, orc, pos.astype(np.float32), 8)
+    assert np.count_nonzero(got.sum(axis=(0, 1))) == 1
+
+
+def test_images_outside_the_box(psd, orc):
+    pos = zeldovich_positions(10, 0.9, seed=45)
+    q = (np.round(pos.astype(np.float64) * 2 ** 16) / 2 ** 16).astype(np.float32)
+    rng = np.random.default_rng(46)
+    shift = rng.integers(-3, 4, size=q.shape[:3] + (1,)).astype(np.float32)
+    moved = (q + shift).astype(np.float32)
+    assert np.array_equal(np.mod(moved.astype(np.float64), 1.0).astype(np.float32), q)
+    a, _, _ = _run(psd, q, 20)
+    b, _, _ = _run(psd, moved, 20)
+    assert _rel_l1(b, a) <= 1e-6
+
+
+def test_box_and_mass_scaling(psd, orc):
+    pos = (zeldovich_positions(8, 0.7, seed=47).astype(np.float64) * 2.5).astype(np.float32)
+    _compare(psd, orc, pos, 16, box=2.5, mass=7.0)
+
+
+def test_density_and_accumulate_flags(psd):
+    pos = zeldovich_positions(8, 0.7, seed=48)
+    nc = 16
+    mass, _, _ = _run(psd, pos, nc, box=2.0)
+    dens, _, _ = _run(psd, pos, nc, box=2.0, flags=psd.PSD_OUT_DENSITY)
+    h3 = (2.0 / nc) ** 3
+    assert np.allclose(dens * h3, mass, rtol=1e-6, atol=0)
+    dev = torch.device("cuda:0")
+    pt = torch.from_numpy(pos).to(dev)
+    out = torch.full((nc, nc, nc), 0.5, dtype=torch.float32, device=dev)
+    psd.deposit_uniform(pt, nc, box=2.0, flags=psd.PSD_ACCUMULATE, out=out)
+    psd.deposit_uniform(pt, nc, box=2.0, flags=psd.PSD_ACCUMULATE, out=out)
+    torch.cuda.synchronize()
+    assert np.allclose(out.double().cpu().numpy(), 0.5 + 2 * mass, rtol=1e-6, atol=1e-9)
+
+
+@functools.lru_cache(maxsize=1)
+def _zel256():
+    return workload("zel256_g512")
+
+
+@pytest.mark.parametrize("method", list(METHODS))
+def test_zel256_g512_sampled_blocks(psd, orc, method):
+    """Full size (100.7M tets -> 512^3): oracle on sampled 16^3 blocks, global mass."""
+    pos, p = _zel256()
+    nc = p["nc"]
+    got, msum, st = _run(psd, pos, nc, flags=METHODS[method])
+    assert st[0] == 6 * 256 ** 3
+    assert abs(msum - 1.0) <= 1e-6
+    assert abs(got.sum() - 1.0) <= 1e-5
+    rng = np.random.default_rng(2)
+    for _ in range(2):
+        lo = [int(x) for x in rng.integers(0, nc - 16, size=3)]
+        ref, _ = orc.deposit_uniform(pos, nc, region=(lo, (16, 16, 16)))
+        blk = got[lo[0]:lo[0] + 16, lo[1]:lo[1] + 16, lo[2]:lo[2] + 16]
+        l1 = _rel_l1(blk, ref)
+        print(f"block {lo}: L1 {l1:.3e} Linf {_rel_linf(blk, ref):.3e}")
+        assert l1 <= FP32_L1
