@@ -98,6 +98,70 @@ psd_status psd_deposit_uniform(const float* pos, const psd_particles* p, const i
                                void* out, double* mass_sum, const psd_options* opt, void* ws,
                                size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Adaptive octree (Section 4)                                               */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t block_cells; /* B: cells per leaf side (the paper's tests use 128
+                            and 64; 16 here), >= 1                            */
+    int32_t max_level;   /* refinements below the root, 0..7                 */
+    int32_t subblock;    /* Lagrangian cubes per subblock side (paper: 8)    */
+    int32_t reserved;    /* must be 0                                        */
+    int64_t threshold;   /* a node is refined iff its count > threshold      */
+} psd_octree_params;
+
+typedef struct {
+    int32_t level;       /* 0 = root (the whole periodic box)                */
+    int32_t ix, iy, iz;  /* position among the 2^level nodes per axis        */
+    int32_t first_child; /* index of the first of 8 contiguous children, or -1 */
+    int32_t leaf_id;     /* leaf number (node order) or -1                   */
+    int64_t count;       /* overlap estimate of tetrahedra in the node       */
+} psd_octree_node;
+
+/* Workspace bytes (host out) for psd_build_octree and psd_deposit_octree. */
+psd_status psd_octree_workspace_size(const psd_particles* p, const psd_octree_params* op,
+                                     size_t* bytes);
+
+/*
+ * Octree refined where many tetrahedra overlap (Section 4): starting from
+ * the root box, a node is split into 8 children while its count exceeds
+ * `threshold` and its level is below `max_level`.  The count is the paper's
+ * memory-efficient estimate from Lagrangian subblocks of subblock^3 cubes,
+ * made integer-exact: sum over subblocks of floor(ntets * |bbox cap node| /
+ * |bbox|), bounding boxes (min/max of the subblock's unwrapped cube corners)
+ * snapped outward to the finest lattice G = B * 2^max_level, overlaps over
+ * periodic images.  The result is bit-reproducible.
+ *   nodes     DEVICE psd_octree_node[capacity]: canonical order -- by level,
+ *             Morton order (x most significant) within a level, the 8
+ *             children of a node contiguous -- leaves numbered in node order
+ *   n_nodes, n_leaves  host out
+ * Returns PSD_ERR_CAPACITY (with *n_nodes, *n_leaves set) when capacity is
+ * too small.  Synchronizes `stream`.
+ */
+psd_status psd_build_octree(const float* pos, const psd_particles* p, const psd_octree_params* op,
+                            psd_octree_node* nodes, int64_t capacity, int64_t* n_nodes,
+                            int64_t* n_leaves, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Cell masses (densities with PSD_OUT_DENSITY) of the octree's leaves: a leaf
+ * at level l covers box/2^l per axis with B^3 cells of side box/(B 2^l);
+ * tetrahedra crossing leaves deposit into each (Section 4 leaf patches,
+ * Section 6 deposit).  Same exact volumes as psd_deposit_uniform at the
+ * leaf's resolution.
+ *   nodes     DEVICE array from psd_build_octree (n_nodes entries)
+ *   out       DEVICE float [n_leaves][B][B][B], zeroed first unless
+ *             PSD_ACCUMULATE
+ *   mass_sum  DEVICE double[1] or NULL (FP64 sum of deposited mass)
+ *   flags     PSD_OUT_DENSITY, PSD_ACCUMULATE
+ * Errors: PSD_ERR_ARG, PSD_ERR_WORKSPACE, PSD_ERR_UNSUPPORTED, PSD_ERR_HIP.
+ * Asynchronous.
+ */
+psd_status psd_deposit_octree(const float* pos, const psd_particles* p, const psd_octree_params* op,
+                              const psd_octree_node* nodes, int64_t n_nodes, int64_t n_leaves,
+                              float* out, double* mass_sum, const psd_options* opt, void* ws,
+                              size_t ws_bytes, void* stream);
+
 /* Human-readable name of a status code (static string). */
 const char* psd_status_string(psd_status s);
 

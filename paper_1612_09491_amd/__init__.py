@@ -152,3 +152,125 @@ def deposit_uniform(pos: torch.Tensor, nc, box: float = 1.0, mass: float = 1.0, 
                                      _stream_handle(stream)),
            "psd_deposit_uniform")
     return out
+
+
+# ---------------------------------------------------------------------------
+# Octree
+# ---------------------------------------------------------------------------
+
+class OctreeParams(C.Structure):
+    _fields_ = [("block_cells", C.c_int32), ("max_level", C.c_int32), ("subblock", C.c_int32),
+                ("reserved", C.c_int32), ("threshold", C.c_int64)]
+
+
+NODE_BYTES = 32
+NODE_FIELDS = (("level", "<i4"), ("ix", "<i4"), ("iy", "<i4"), ("iz", "<i4"),
+               ("first_child", "<i4"), ("leaf_id", "<i4"), ("count", "<i8"))
+
+
+def _octree_params(block, max_level, subblock, threshold) -> OctreeParams:
+    return OctreeParams(int(block), int(max_level), int(subblock), 0, int(threshold))
+
+
+def _bind_octree(L):
+    if getattr(L, "_octree_bound", False):
+        return
+    L.psd_octree_workspace_size.restype = C.c_int
+    L.psd_octree_workspace_size.argtypes = [C.POINTER(Particles), C.POINTER(OctreeParams),
+                                            C.POINTER(C.c_size_t)]
+    L.psd_build_octree.restype = C.c_int
+    L.psd_build_octree.argtypes = [C.c_void_p, C.POINTER(Particles), C.POINTER(OctreeParams),
+                                   C.c_void_p, C.c_int64, C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_int64), C.c_void_p, C.c_size_t, C.c_void_p]
+    L.psd_deposit_octree.restype = C.c_int
+    L.psd_deposit_octree.argtypes = [C.c_void_p, C.POINTER(Particles), C.POINTER(OctreeParams),
+                                     C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
+                                     C.POINTER(Options), C.c_void_p, C.c_size_t, C.c_void_p]
+    L._octree_bound = True
+
+
+def max_nodes(max_level: int) -> int:
+    return sum(8 ** l for l in range(max_level + 1))
+
+
+def octree_workspace_size(np_, block=16, max_level=4, subblock=8, threshold=1 << 20,
+                          box: float = 1.0, mass: float = 1.0) -> int:
+    L = lib()
+    _bind_octree(L)
+    p = Particles()
+    for a, n in enumerate(_grid3(np_)):
+        p.np[a] = n
+    p.box, p.total_mass = float(box), float(mass)
+    op = _octree_params(block, max_level, subblock, threshold)
+    nbytes = C.c_size_t(0)
+    _check(L.psd_octree_workspace_size(C.byref(p), C.byref(op), C.byref(nbytes)),
+           "psd_octree_workspace_size")
+    return int(nbytes.value)
+
+
+class Octree:
+    """Device node array plus its sizes and build parameters."""
+
+    def __init__(self, nodes: torch.Tensor, n_nodes: int, n_leaves: int, block: int,
+                 max_level: int, subblock: int, threshold: int):
+        self.nodes, self.n_nodes, self.n_leaves = nodes, n_nodes, n_leaves
+        self.block, self.max_level, self.subblock, self.threshold = block, max_level, subblock, threshold
+
+    def to_numpy(self):
+        import numpy as np
+        raw = self.nodes[: self.n_nodes * NODE_BYTES].cpu().numpy()
+        return raw.view(np.dtype(list(NODE_FIELDS)))
+
+
+def build_octree(pos: torch.Tensor, block: int = 16, max_level: int = 4, subblock: int = 8,
+                 threshold: int = 1 << 20, box: float = 1.0, capacity: int | None = None,
+                 workspace: torch.Tensor | None = None, stream=None) -> Octree:
+    """Adaptive octree of psd_build_octree (synchronizes the stream)."""
+    L = lib()
+    _bind_octree(L)
+    p = _particles(pos, box, 1.0)
+    op = _octree_params(block, max_level, subblock, threshold)
+    cap = max_nodes(max_level) if capacity is None else int(capacity)
+    nodes = torch.empty(max(cap, 1) * NODE_BYTES, dtype=torch.uint8, device=pos.device)
+    nbytes = octree_workspace_size(tuple(pos.shape[:3]), block, max_level, subblock, threshold, box)
+    if workspace is None:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=pos.device)
+    nn, nl = C.c_int64(0), C.c_int64(0)
+    code = L.psd_build_octree(pos.data_ptr(), C.byref(p), C.byref(op), nodes.data_ptr(), cap,
+                              C.byref(nn), C.byref(nl), workspace.data_ptr(), workspace.numel(),
+                              _stream_handle(stream))
+    if code == PSD_ERR_CAPACITY:
+        err = PsdError(code, "psd_build_octree", f"needs {nn.value} nodes")
+        err.n_nodes, err.n_leaves = int(nn.value), int(nl.value)
+        raise err
+    _check(code, "psd_build_octree")
+    return Octree(nodes, int(nn.value), int(nl.value), block, max_level, subblock, threshold)
+
+
+def deposit_octree(pos: torch.Tensor, tree: Octree, box: float = 1.0, mass: float = 1.0,
+                   flags: int = 0, out: torch.Tensor | None = None,
+                   mass_sum: torch.Tensor | None = None, stats: torch.Tensor | None = None,
+                   workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Leaf cell masses (or densities) [n_leaves, B, B, B] float32."""
+    L = lib()
+    _bind_octree(L)
+    p = _particles(pos, box, mass)
+    op = _octree_params(tree.block, tree.max_level, tree.subblock, tree.threshold)
+    B = tree.block
+    shape = (tree.n_leaves, B, B, B)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=pos.device)
+    elif out.dtype != torch.float32 or tuple(out.shape) != shape or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous float32 tensor of shape {shape}")
+    nbytes = octree_workspace_size(tuple(pos.shape[:3]), tree.block, tree.max_level, tree.subblock,
+                                   tree.threshold, box)
+    if workspace is None:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=pos.device)
+    o = Options(flags, stats.data_ptr() if stats is not None else None)
+    _check(L.psd_deposit_octree(pos.data_ptr(), C.byref(p), C.byref(op), tree.nodes.data_ptr(),
+                                tree.n_nodes, tree.n_leaves, out.data_ptr(),
+                                mass_sum.data_ptr() if mass_sum is not None else None,
+                                C.byref(o), workspace.data_ptr(), workspace.numel(),
+                                _stream_handle(stream)),
+           "psd_deposit_octree")
+    return out

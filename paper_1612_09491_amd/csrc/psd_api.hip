@@ -43,6 +43,32 @@ bool grid_ok(const int32_t nc[3])
 }
 
 constexpr size_t kUniformWorkspace = 256;
+
+bool octree_params_ok(const psd_octree_params* op)
+{
+    return op && op->block_cells >= 1 && op->block_cells <= 4096 && op->max_level >= 0 &&
+           op->max_level <= 7 && op->subblock >= 1 && op->reserved == 0 && op->threshold >= 0 &&
+           ((int64_t)op->block_cells << op->max_level) <= (1 << 20);
+}
+
+psd::OctreeArgs octree_args(const float* pos, const psd_particles* p, const psd_octree_params* op)
+{
+    psd::OctreeArgs A;
+    memset(&A, 0, sizeof(A));
+    A.pos = pos;
+    for (int a = 0; a < 3; ++a) {
+        A.np[a] = p->np[a];
+        A.ns[a] = (p->np[a] + op->subblock - 1) / op->subblock;
+    }
+    A.box = p->box;
+    A.block = op->block_cells;
+    A.max_level = op->max_level;
+    A.subblock = op->subblock;
+    A.G = (int64_t)op->block_cells << op->max_level;
+    A.gscale = (double)A.G / p->box;
+    A.threshold = op->threshold;
+    return A;
+}
 constexpr uint32_t kUniformFlags = PSD_OUT_DENSITY | PSD_ACCUMULATE | PSD_PREC_FP64 | PSD_METHOD_CELL;
 
 }  // namespace
@@ -109,6 +135,74 @@ psd_status psd_deposit_uniform(const float* pos, const psd_particles* p, const i
                                                (flags & PSD_METHOD_CELL) != 0,
                                                reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) return fail_hip(e, "deposit_uniform launch");
+    return PSD_OK;
+}
+
+psd_status psd_octree_workspace_size(const psd_particles* p, const psd_octree_params* op,
+                                     size_t* bytes)
+{
+    if (!bytes) return fail(PSD_ERR_ARG, "bytes is null");
+    if (!particles_ok(p)) return fail(PSD_ERR_ARG, "bad particle description");
+    if (!octree_params_ok(op)) return fail(PSD_ERR_ARG, "bad octree parameters");
+    *bytes = psd::octree_workspace_layout(octree_args(nullptr, p, op)).bytes;
+    return PSD_OK;
+}
+
+psd_status psd_build_octree(const float* pos, const psd_particles* p, const psd_octree_params* op,
+                            psd_octree_node* nodes, int64_t capacity, int64_t* n_nodes,
+                            int64_t* n_leaves, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!pos || !n_nodes || !n_leaves) return fail(PSD_ERR_ARG, "null pointer");
+    if (!particles_ok(p)) return fail(PSD_ERR_ARG, "bad particle description");
+    if (!octree_params_ok(op)) return fail(PSD_ERR_ARG, "bad octree parameters");
+    if (capacity < 0 || (capacity > 0 && !nodes)) return fail(PSD_ERR_ARG, "bad node array");
+    const psd::OctreeArgs A = octree_args(pos, p, op);
+    if (!ws || ws_bytes < psd::octree_workspace_layout(A).bytes)
+        return fail(PSD_ERR_WORKSPACE, "workspace too small");
+    int64_t counts[2] = {0, 0};
+    hipError_t e = psd::launch_build_octree(A, ws, reinterpret_cast<psd::OctNode*>(nodes), capacity,
+                                            counts, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail_hip(e, "build_octree");
+    *n_nodes = counts[0];
+    *n_leaves = counts[1];
+    if (counts[0] > capacity) return fail(PSD_ERR_CAPACITY, "node array too small");
+    return PSD_OK;
+}
+
+psd_status psd_deposit_octree(const float* pos, const psd_particles* p, const psd_octree_params* op,
+                              const psd_octree_node* nodes, int64_t n_nodes, int64_t n_leaves,
+                              float* out, double* mass_sum, const psd_options* opt, void* ws,
+                              size_t ws_bytes, void* stream)
+{
+    if (!pos || !nodes || !out) return fail(PSD_ERR_ARG, "null pointer");
+    if (!particles_ok(p)) return fail(PSD_ERR_ARG, "bad particle description");
+    if (!octree_params_ok(op)) return fail(PSD_ERR_ARG, "bad octree parameters");
+    if (n_nodes < 1 || n_leaves < 1 || n_leaves > n_nodes ||
+        n_nodes > psd::octree_max_nodes(op->max_level))
+        return fail(PSD_ERR_ARG, "bad node or leaf count");
+    const uint32_t flags = opt ? opt->flags : 0u;
+    if (flags & ~(uint32_t)(PSD_OUT_DENSITY | PSD_ACCUMULATE))
+        return fail(PSD_ERR_UNSUPPORTED, "octree deposit supports PSD_OUT_DENSITY and PSD_ACCUMULATE");
+    const psd::OctreeArgs A = octree_args(pos, p, op);
+    if (!ws || ws_bytes < psd::octree_workspace_layout(A).bytes)
+        return fail(PSD_ERR_WORKSPACE, "workspace too small");
+    psd::UniformArgs U;
+    memset(&U, 0, sizeof(U));
+    U.pos = pos;
+    for (int a = 0; a < 3; ++a) U.np[a] = p->np[a];
+    U.ntet = 6 * (int64_t)p->np[0] * p->np[1] * p->np[2];
+    U.m = p->total_mass / (6.0 * (double)p->np[0] * (double)p->np[1] * (double)p->np[2]);
+    U.out_scale = (flags & PSD_OUT_DENSITY) ? 0.0 : 1.0;  // per level when density
+    U.out = out;
+    U.mass_sum = mass_sum;
+    U.stats = opt ? reinterpret_cast<unsigned long long*>(opt->stats) : nullptr;
+    U.grid_limit = 256 * 32;
+    const int64_t B = op->block_cells;
+    hipError_t e = psd::launch_deposit_octree(A, U, reinterpret_cast<const psd::OctNode*>(nodes),
+                                              n_nodes, n_leaves * B * B * B, ws,
+                                              (flags & PSD_ACCUMULATE) != 0,
+                                              reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail_hip(e, "deposit_octree launch");
     return PSD_OK;
 }
 

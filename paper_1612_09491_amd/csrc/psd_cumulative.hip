@@ -41,8 +41,18 @@ struct CTet {
 struct Tile {
     int a0, ta, b0, tb, l0, tl;
     int ha, hb;
-    int doff;  // offset in the D buffer
+    int doff;        // offset in the D buffer
+    float inv_wb;    // 1 / (tb + hb)
+    float inv_tb;    // 1 / tb
+    float inv_tl;    // 1 / tl
 };
+
+// q = n / d for 0 <= n < 2^20 via a float reciprocal (exact in that range:
+// the error of (n + 1/2) * (1/d) stays below 1/(2d)).
+__device__ __forceinline__ int fdivi(int n, float inv_d)
+{
+    return (int)(((float)n + 0.5f) * inv_d);
+}
 
 // Tile shape for a tetrahedron whose D array exceeds the buffer:
 // (ta+1)*(tb+1)*tl <= kCap with ta, tb >= 1.
@@ -64,29 +74,107 @@ __device__ __forceinline__ int wrap_add(int base, int off, int n)
     return x >= n ? x - n : x;
 }
 
-// Fraction of the tetrahedron with vertex heights z[] lying at z <= k.
-__device__ __forceinline__ double below(const double z[4], double k)
+// Output index of grid cell (x,y,z) (wrapped into [0,nc)), or -1 when the
+// cell belongs to no leaf of this level.
+__device__ __forceinline__ int64_t out_index(const UniformArgs& P, int x, int y, int z)
 {
-    double d[4] = {k - z[0], k - z[1], k - z[2], k - z[3]};
-    Split<double> s;
-    split_plane(d, s);
-    return s.f0 + s.f1 + s.f2;
+    if (!P.leaf_map) return ((int64_t)x * P.nc[1] + y) * P.nc[2] + z;
+    const int B = P.leaf_block, side = P.leaf_side;
+    const int nx = x / B, ny = y / B, nz = z / B;
+    const int leaf = P.leaf_map[(nx * side + ny) * side + nz];
+    if (leaf < 0) return -1;
+    return (int64_t)leaf * B * B * B + ((x - nx * B) * B + (y - ny * B)) * B + (z - nz * B);
+}
+
+// Does the wrapped box [lo, lo+ext) meet a leaf of this level?  Boxes wider
+// than a few nodes are not tested (they are simply processed).
+__device__ __forceinline__ bool touches_leaf(const UniformArgs& P, const int lo[3], const int ext[3])
+{
+    const int B = P.leaf_block, side = P.leaf_side;
+    int n0[3], nn[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        n0[c] = lo[c] / B;
+        nn[c] = (lo[c] + ext[c] - 1) / B - n0[c] + 1;
+        if (nn[c] > 4) return true;
+    }
+    for (int a = 0; a < nn[0]; ++a)
+        for (int b = 0; b < nn[1]; ++b)
+            for (int c = 0; c < nn[2]; ++c) {
+                const int x = (n0[0] + a) % side, y = (n0[1] + b) % side, z = (n0[2] + c) % side;
+                if (P.leaf_map[(x * side + y) * side + z] >= 0) return true;
+            }
+    return false;
+}
+
+// Distribution of height z over one tetrahedral piece.  With the vertex
+// heights sorted, s0 <= s1 <= s2 <= s3, the fraction of the piece below a
+// plane z = k is a piecewise cubic:
+//   s0 < k <= s1 : u^3 / ((s1-s0)(s2-s0)(s3-s0)),      u = k - s0
+//   s2 <= k < s3 : 1 - w^3 / ((s3-s0)(s3-s1)(s3-s2)),  w = s3 - k
+//   s1 < k < s2  : t02 t03 (1 - t13) + t02 (1 - t12) t13 + t12 t13,
+//                  t0j = (k - s0)/(sj - s0), t1j = (k - s1)/(sj - s1)
+// (the inside-part fractions of a plane split, Section 6.3's table, for a
+// plane parallel to the cell faces; every term is a product of factors in
+// [0, 1], so nothing cancels).
+struct ZDist {
+    double s0, s1, s2, s3;
+    double iA, iC;            // reciprocal products of the two end regions
+    double r20, r30, r21, r31;
+};
+
+__device__ __forceinline__ double rcp_or0(double d) { return d > 0.0 ? fdiv_pos(1.0, d) : 0.0; }
+
+__device__ __forceinline__ void zdist_init(const double z[4], ZDist& Z)
+{
+    double a = fmin(z[0], z[1]), b = fmax(z[0], z[1]);
+    double c = fmin(z[2], z[3]), d = fmax(z[2], z[3]);
+    const double s0 = fmin(a, c), t1 = fmax(a, c);
+    const double s3 = fmax(b, d), t2 = fmin(b, d);
+    Z.s0 = s0;
+    Z.s1 = fmin(t1, t2);
+    Z.s2 = fmax(t1, t2);
+    Z.s3 = s3;
+    const double d10 = Z.s1 - s0, d20 = Z.s2 - s0, d30 = s3 - s0;
+    const double d21 = Z.s2 - Z.s1, d31 = s3 - Z.s1, d32 = s3 - Z.s2;
+    Z.r20 = rcp_or0(d20);
+    Z.r30 = rcp_or0(d30);
+    Z.r21 = rcp_or0(d21);
+    Z.r31 = rcp_or0(d31);
+    Z.iA = rcp_or0(d10 * d20 * d30);
+    Z.iC = rcp_or0(d30 * d31 * d32);
+}
+
+__device__ __forceinline__ double zdist_below(const ZDist& Z, double k)
+{
+    if (k <= Z.s0) return 0.0;
+    if (k >= Z.s3) return 1.0;
+    if (k <= Z.s1) {
+        const double u = k - Z.s0;
+        return u * u * u * Z.iA;
+    }
+    if (k >= Z.s2) {
+        const double w = Z.s3 - k;
+        return 1.0 - w * w * w * Z.iC;
+    }
+    const double t02 = (k - Z.s0) * Z.r20, t03 = (k - Z.s0) * Z.r30;
+    const double t12 = (k - Z.s1) * Z.r21, t13 = (k - Z.s1) * Z.r31;
+    return t02 * t03 * (1.0 - t13) + t02 * (1.0 - t12) * t13 + t12 * t13;
 }
 
 // Adds frac * (share of each z-cell of the tile) for one piece.
 __device__ __forceinline__ void spread_z(const double z[4], double frac, const Tile& t,
                                          double* Dcol)
 {
-    const double zmin = fmin(fmin(z[0], z[1]), fmin(z[2], z[3]));
-    const double zmax = fmax(fmax(z[0], z[1]), fmax(z[2], z[3]));
-    const int lfirst = (int)floor(zmin);
+    ZDist Z;
+    zdist_init(z, Z);
+    const int lfirst = (int)floor(Z.s0);
     const int lA = max(lfirst, t.l0);
-    const int lB = min((int)floor(zmax), t.l0 + t.tl - 1);
+    const int lB = min((int)floor(Z.s3), t.l0 + t.tl - 1);
     if (lA > lB) return;
-    double Fprev = (lA <= lfirst) ? 0.0 : below(z, (double)lA);
+    double Fprev = (lA <= lfirst) ? 0.0 : zdist_below(Z, (double)lA);
     for (int l = lA; l <= lB; ++l) {
-        const double kn = (double)(l + 1);
-        const double Fnext = (kn >= zmax) ? 1.0 : below(z, kn);
+        const double Fnext = zdist_below(Z, (double)(l + 1));
         Dcol[l - t.l0] += frac * (Fnext - Fprev);
         Fprev = Fnext;
     }
@@ -188,6 +276,7 @@ __global__ __launch_bounds__(kWave) void deposit_cumulative_kernel(UniformArgs P
     __shared__ int t_slot[kWave];
     __shared__ int64_t s_incl[kWave];
 
+    if (P.level_has_leaf && *P.level_has_leaf == 0) return;
     OutT* out = reinterpret_cast<OutT*>(P.out);
     const int lane = threadIdx.x;
     const double sc[3] = {P.scale[0], P.scale[1], P.scale[2]};
@@ -222,9 +311,11 @@ __global__ __launch_bounds__(kWave) void deposit_cumulative_kernel(UniformArgs P
                     const double n = (double)P.nc[c];
                     g[c] = (int)(fl - n * floor(fl / n));
                 }
-                const int64_t idx = ((int64_t)g[0] * P.nc[1] + g[1]) * P.nc[2] + g[2];
-                atomicAdd(out + idx, (OutT)(P.m * P.out_scale));
-                macc += P.m;
+                const int64_t idx = out_index(P, g[0], g[1], g[2]);
+                if (idx >= 0) {
+                    atomicAdd(out + idx, (OutT)(P.m * P.out_scale));
+                    macc += P.m;
+                }
             } else {
                 CTet& S = slots[lane];
                 bool ok = true;
@@ -242,15 +333,18 @@ __global__ __launch_bounds__(kWave) void deposit_cumulative_kernel(UniformArgs P
                     for (int q = 0; q < 4; ++q) S.vr[q][c] = T.v[q][c] - lo;
                 }
                 ncell = ok ? S.ext[0] * S.ext[1] * S.ext[2] : 0;
+                if (ncell && P.leaf_map && !touches_leaf(P, S.lo, S.ext)) ncell = 0;
                 S.ncell = ncell;
                 S.ncol = ok ? S.ext[0] * S.ext[1] : 0;
                 if (ncell == 1) {
                     // the tetrahedron lies inside one cell
                     ++n_pair;
                     ++n_nz;
-                    const int64_t idx = ((int64_t)S.lo[0] * P.nc[1] + S.lo[1]) * P.nc[2] + S.lo[2];
-                    atomicAdd(out + idx, (OutT)(P.m * P.out_scale));
-                    macc += P.m;
+                    const int64_t idx = out_index(P, S.lo[0], S.lo[1], S.lo[2]);
+                    if (idx >= 0) {
+                        atomicAdd(out + idx, (OutT)(P.m * P.out_scale));
+                        macc += P.m;
+                    }
                     ncell = 0;
                     S.ncell = 0;
                 }
@@ -294,6 +388,9 @@ __global__ __launch_bounds__(kWave) void deposit_cumulative_kernel(UniformArgs P
                 const int ds = tile_dsize(t);
                 if (used + ds > kCap) break;  // buffer full: run this batch first
                 t.doff = used;
+                t.inv_wb = 1.0f / (float)(t.tb + t.hb);
+                t.inv_tb = 1.0f / (float)t.tb;
+                t.inv_tl = 1.0f / (float)t.tl;
                 used += ds;
                 if (lane == 0) {
                     tiles[nt] = t;
@@ -333,8 +430,9 @@ __global__ __launch_bounds__(kWave) void deposit_cumulative_kernel(UniformArgs P
                         const CTet& S = slots[t_slot[lo]];
                         const int r = (int)(idx - (s_incl[lo] - tile_cols(t)));
                         const int wb = t.tb + t.hb;
-                        const int a = t.a0 - t.ha + r / wb;
-                        const int b = t.b0 - t.hb + r % wb;
+                        const int qa = fdivi(r, t.inv_wb);
+                        const int a = t.a0 - t.ha + qa;
+                        const int b = t.b0 - t.hb + (r - qa * wb);
                         column(S, a, b, t, Dbuf + t.doff + r * t.tl);
                         ++n_col;
                     }
@@ -366,10 +464,10 @@ __global__ __launch_bounds__(kWave) void deposit_cumulative_kernel(UniformArgs P
                         const CTet& S = slots[t_slot[lo]];
                         const int r = (int)(idx - (s_incl[lo] - tile_cells(t)));
                         // r -> (i, j, l) within the tile, l fastest
-                        const int l = r % t.tl;
-                        const int ij = r / t.tl;
-                        const int j = ij % t.tb;
-                        const int i = ij / t.tb;
+                        const int ij = fdivi(r, t.inv_tl);
+                        const int l = r - ij * t.tl;
+                        const int i = fdivi(ij, t.inv_tb);
+                        const int j = ij - i * t.tb;
                         const int wb = t.tb + t.hb;
                         const double* D = Dbuf + t.doff;
                         // column index of (a, b) = (t.a0 + i, t.b0 + j) in the buffer
@@ -387,10 +485,12 @@ __global__ __launch_bounds__(kWave) void deposit_cumulative_kernel(UniformArgs P
                             const int gx = wrap_add(S.lo[0], t.a0 + i, P.nc[0]);
                             const int gy = wrap_add(S.lo[1], t.b0 + j, P.nc[1]);
                             const int gz = wrap_add(S.lo[2], t.l0 + l, P.nc[2]);
-                            const int64_t gi = ((int64_t)gx * P.nc[1] + gy) * P.nc[2] + gz;
-                            const double mass = P.m * V;
-                            atomicAdd(out + gi, (OutT)(mass * P.out_scale));
-                            macc += mass;
+                            const int64_t gi = out_index(P, gx, gy, gz);
+                            if (gi >= 0) {
+                                const double mass = P.m * V;
+                                atomicAdd(out + gi, (OutT)(mass * P.out_scale));
+                                macc += mass;
+                            }
                         }
                     }
                 }

@@ -166,11 +166,12 @@ def test_density_and_accumulate_flags(psd):
     assert np.allclose(dens * h3, mass, rtol=1e-6, atol=0)
     dev = torch.device("cuda:0")
     pt = torch.from_numpy(pos).to(dev)
-    out = torch.full((nc, nc, nc), 0.5, dtype=torch.float32, device=dev)
+    base = np.float32(1e-3)
+    out = torch.full((nc, nc, nc), float(base), dtype=torch.float32, device=dev)
     psd.deposit_uniform(pt, nc, box=2.0, flags=psd.PSD_ACCUMULATE, out=out)
     psd.deposit_uniform(pt, nc, box=2.0, flags=psd.PSD_ACCUMULATE, out=out)
     torch.cuda.synchronize()
-    assert np.allclose(out.double().cpu().numpy(), 0.5 + 2 * mass, rtol=1e-6, atol=1e-9)
+    assert np.allclose(out.double().cpu().numpy(), float(base) + 2 * mass, rtol=1e-6, atol=1e-10)
 
 
 @functools.lru_cache(maxsize=1)
