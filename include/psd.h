@@ -64,12 +64,24 @@ typedef struct {
     double total_mass; /* mass of all particles                               */
 } psd_particles;
 
+/* Launch shape of the cumulative deposit (all zero = defaults). */
+typedef struct {
+    int32_t lds_cap;      /* FP64 entries of the per-wavefront LDS buffer:
+                             512, 1024 or 2048 (0 = 1024)                     */
+    int32_t waves_per_cu; /* persistent wavefronts per compute unit (0 = 8)   */
+    int32_t ordered;      /* 1: process 64-tet chunks in decreasing estimated
+                             cost (bbox cells); 0: in index order             */
+    int32_t reserved;     /* must be 0                                        */
+} psd_tuning;
+
 typedef struct {
     uint32_t flags;    /* PSD_* flags above                                   */
     int64_t* stats;    /* optional DEVICE int64[8] counters, added into:
                           [0] tets, [1] (tet, bbox cell) pairs, [2] exact
-                          clips, [3] non-zero deposits, [4] inverted tets,
+                          clips (per-cell method) or bbox columns (cumulative),
+                          [3] non-zero deposits, [4] inverted tets,
                           [5] zero-volume tets, [6..7] reserved; may be NULL */
+    const psd_tuning* tuning; /* host, may be NULL                           */
 } psd_options;
 
 /* Workspace bytes (host out) needed by psd_deposit_uniform for this problem. */
@@ -97,6 +109,52 @@ psd_status psd_uniform_workspace_size(const psd_particles* p, const int32_t nc[3
 psd_status psd_deposit_uniform(const float* pos, const psd_particles* p, const int32_t nc[3],
                                void* out, double* mass_sum, const psd_options* opt, void* ws,
                                size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Many independent boxes in one launch                                      */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    const float* pos;  /* DEVICE float [np0][np1][np2][3] of this box          */
+    psd_particles p;   /* its Lagrangian grid, box side and total mass         */
+    int32_t nc[3];     /* its periodic deposit grid                           */
+    float* out;        /* DEVICE float [nc0][nc1][nc2]                        */
+} psd_box;
+
+/* Workspace bytes (host out) for psd_deposit_batched with these options. */
+psd_status psd_batched_workspace_size(const psd_box* boxes, int32_t n_boxes,
+                                      const psd_options* opt, size_t* bytes);
+
+/*
+ * Deposits every box of a batch (each box exactly as psd_deposit_uniform
+ * with the default method would) in one persistent launch.  Workgroups pop
+ * 64-tetrahedron chunks of all boxes from one device counter; with
+ * tuning->ordered the chunks are first binned by their bbox cell count and
+ * processed from the most to the least expensive, which balances boxes of
+ * very different size (the kernel-level load balancing of Section 5).
+ *   boxes      host array of n_boxes descriptors (n_boxes >= 1)
+ *   mass_sums  DEVICE double[n_boxes] or NULL: per-box FP64 mass sums
+ *   flags      PSD_OUT_DENSITY, PSD_ACCUMULATE
+ * Errors: PSD_ERR_ARG, PSD_ERR_WORKSPACE, PSD_ERR_UNSUPPORTED, PSD_ERR_HIP.
+ * Asynchronous.
+ */
+psd_status psd_deposit_batched(const psd_box* boxes, int32_t n_boxes, double* mass_sums,
+                               const psd_options* opt, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Chooses the launch shape (psd_tuning) of psd_deposit_batched for this batch
+ * by timing candidates with HIP events on `stream`: LDS buffer of 1024 or
+ * 2048 FP64 entries, 4 or 8 wavefronts per compute unit, chunks in index or
+ * cost order.  The boxes' outputs are overwritten with a valid deposit.  If
+ * cache_path (host string, may be NULL) names a JSON file, a result for the
+ * same device and batch signature is read from it instead of measuring, and
+ * new results are added to it.  The workspace must be sized for ordered
+ * chunks (psd_batched_workspace_size with tuning->ordered = 1).
+ * Synchronizes `stream`.
+ */
+psd_status psd_autotune_batched(const psd_box* boxes, int32_t n_boxes, const psd_options* opt,
+                                void* ws, size_t ws_bytes, void* stream, const char* cache_path,
+                                psd_tuning* best, double* best_ms);
 
 /* ------------------------------------------------------------------------ */
 /* Adaptive octree (Section 4)                                               */

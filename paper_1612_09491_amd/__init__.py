@@ -43,8 +43,22 @@ class Particles(C.Structure):
     _fields_ = [("np", C.c_int32 * 3), ("box", C.c_double), ("total_mass", C.c_double)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("lds_cap", C.c_int32), ("waves_per_cu", C.c_int32), ("ordered", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
 class Options(C.Structure):
-    _fields_ = [("flags", C.c_uint32), ("stats", C.c_void_p)]
+    _fields_ = [("flags", C.c_uint32), ("stats", C.c_void_p), ("tuning", C.POINTER(Tuning))]
+
+
+def _options(flags: int, stats, tuning) -> Options:
+    o = Options(flags, stats.data_ptr() if stats is not None else None, None)
+    if tuning is not None:
+        t = Tuning(*[int(x) for x in tuning], 0) if not isinstance(tuning, Tuning) else tuning
+        o._tuning_ref = t
+        o.tuning = C.pointer(t)
+    return o
 
 
 _lib = None
@@ -107,13 +121,14 @@ def _particles(pos: torch.Tensor, box: float, mass: float) -> Particles:
     return p
 
 
-def uniform_workspace_size(np_, nc, flags: int = 0, box: float = 1.0, mass: float = 1.0) -> int:
+def uniform_workspace_size(np_, nc, flags: int = 0, box: float = 1.0, mass: float = 1.0,
+                           tuning=None) -> int:
     p = Particles()
     for a, n in enumerate(_grid3(np_)):
         p.np[a] = n
     p.box, p.total_mass = float(box), float(mass)
     ncs = (C.c_int32 * 3)(*_grid3(nc))
-    o = Options(flags, None)
+    o = _options(flags, None, tuning)
     nbytes = C.c_size_t(0)
     _check(lib().psd_uniform_workspace_size(C.byref(p), ncs, C.byref(o), C.byref(nbytes)),
            "psd_uniform_workspace_size")
@@ -123,7 +138,7 @@ def uniform_workspace_size(np_, nc, flags: int = 0, box: float = 1.0, mass: floa
 def deposit_uniform(pos: torch.Tensor, nc, box: float = 1.0, mass: float = 1.0, flags: int = 0,
                     out: torch.Tensor | None = None, mass_sum: torch.Tensor | None = None,
                     stats: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
-                    stream=None) -> torch.Tensor:
+                    stream=None, tuning=None) -> torch.Tensor:
     """Cell masses (or densities with PSD_OUT_DENSITY) on a periodic nc grid.
 
     Returns ``out`` (float32, or float64 with PSD_PREC_FP64).  ``mass_sum``
@@ -137,14 +152,14 @@ def deposit_uniform(pos: torch.Tensor, nc, box: float = 1.0, mass: float = 1.0, 
         out = torch.empty(g, dtype=dtype, device=pos.device)
     elif out.dtype != dtype or tuple(out.shape) != g or not out.is_contiguous() or not out.is_cuda:
         raise ValueError(f"out must be a contiguous CUDA {dtype} tensor of shape {g}")
-    nbytes = uniform_workspace_size(tuple(pos.shape[:3]), g, flags, box, mass)
+    nbytes = uniform_workspace_size(tuple(pos.shape[:3]), g, flags, box, mass, tuning)
     if workspace is None:
         workspace = torch.empty(nbytes, dtype=torch.uint8, device=pos.device)
     if mass_sum is not None and (mass_sum.dtype != torch.float64 or not mass_sum.is_cuda):
         raise ValueError("mass_sum must be a CUDA float64 tensor")
     if stats is not None and (stats.dtype != torch.int64 or stats.numel() < 8 or not stats.is_cuda):
         raise ValueError("stats must be a CUDA int64 tensor with 8 entries")
-    o = Options(flags, stats.data_ptr() if stats is not None else None)
+    o = _options(flags, stats, tuning)
     ncs = (C.c_int32 * 3)(*g)
     _check(lib().psd_deposit_uniform(pos.data_ptr(), C.byref(p), ncs, out.data_ptr(),
                                      mass_sum.data_ptr() if mass_sum is not None else None,
@@ -250,7 +265,7 @@ def build_octree(pos: torch.Tensor, block: int = 16, max_level: int = 4, subbloc
 def deposit_octree(pos: torch.Tensor, tree: Octree, box: float = 1.0, mass: float = 1.0,
                    flags: int = 0, out: torch.Tensor | None = None,
                    mass_sum: torch.Tensor | None = None, stats: torch.Tensor | None = None,
-                   workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+                   workspace: torch.Tensor | None = None, stream=None, tuning=None) -> torch.Tensor:
     """Leaf cell masses (or densities) [n_leaves, B, B, B] float32."""
     L = lib()
     _bind_octree(L)
@@ -266,7 +281,7 @@ def deposit_octree(pos: torch.Tensor, tree: Octree, box: float = 1.0, mass: floa
                                    tree.threshold, box)
     if workspace is None:
         workspace = torch.empty(nbytes, dtype=torch.uint8, device=pos.device)
-    o = Options(flags, stats.data_ptr() if stats is not None else None)
+    o = _options(flags, stats, tuning)
     _check(L.psd_deposit_octree(pos.data_ptr(), C.byref(p), C.byref(op), tree.nodes.data_ptr(),
                                 tree.n_nodes, tree.n_leaves, out.data_ptr(),
                                 mass_sum.data_ptr() if mass_sum is not None else None,
@@ -274,3 +289,111 @@ def deposit_octree(pos: torch.Tensor, tree: Octree, box: float = 1.0, mass: floa
                                 _stream_handle(stream)),
            "psd_deposit_octree")
     return out
+
+
+# ---------------------------------------------------------------------------
+# Batched boxes and autotuning
+# ---------------------------------------------------------------------------
+
+class Box(C.Structure):
+    _fields_ = [("pos", C.c_void_p), ("p", Particles), ("nc", C.c_int32 * 3), ("out", C.c_void_p)]
+
+
+def _bind_batched(L):
+    if getattr(L, "_batched_bound", False):
+        return
+    L.psd_batched_workspace_size.restype = C.c_int
+    L.psd_batched_workspace_size.argtypes = [C.POINTER(Box), C.c_int32, C.POINTER(Options),
+                                             C.POINTER(C.c_size_t)]
+    L.psd_deposit_batched.restype = C.c_int
+    L.psd_deposit_batched.argtypes = [C.POINTER(Box), C.c_int32, C.c_void_p, C.POINTER(Options),
+                                      C.c_void_p, C.c_size_t, C.c_void_p]
+    L.psd_autotune_batched.restype = C.c_int
+    L.psd_autotune_batched.argtypes = [C.POINTER(Box), C.c_int32, C.POINTER(Options), C.c_void_p,
+                                       C.c_size_t, C.c_void_p, C.c_char_p, C.POINTER(Tuning),
+                                       C.POINTER(C.c_double)]
+    L._batched_bound = True
+
+
+def _box_array(boxes, box: float, mass: float, flags: int):
+    """boxes: list of (pos tensor, nc, out tensor or None) -> (ctypes array, outs)."""
+    arr = (Box * len(boxes))()
+    outs = []
+    for i, item in enumerate(boxes):
+        pos, nc = item[0], _grid3(item[1])
+        out = item[2] if len(item) > 2 else None
+        p = _particles(pos, box, mass)
+        if out is None:
+            out = torch.empty(nc, dtype=torch.float32, device=pos.device)
+        elif out.dtype != torch.float32 or tuple(out.shape) != nc or not out.is_contiguous():
+            raise ValueError(f"box {i}: out must be a contiguous float32 tensor of shape {nc}")
+        arr[i].pos = pos.data_ptr()
+        arr[i].p = p
+        for a in range(3):
+            arr[i].nc[a] = nc[a]
+        arr[i].out = out.data_ptr()
+        outs.append(out)
+    return arr, outs
+
+
+def batched_workspace_size(boxes, flags: int = 0, tuning=None, box: float = 1.0) -> int:
+    L = lib()
+    _bind_batched(L)
+    arr, _ = _box_array(boxes, box, 1.0, flags)
+    o = _options(flags, None, tuning)
+    nbytes = C.c_size_t(0)
+    _check(L.psd_batched_workspace_size(arr, len(arr), C.byref(o), C.byref(nbytes)),
+           "psd_batched_workspace_size")
+    return int(nbytes.value)
+
+
+def deposit_batched(boxes, box: float = 1.0, mass: float = 1.0, flags: int = 0,
+                    mass_sums: torch.Tensor | None = None, stats: torch.Tensor | None = None,
+                    tuning=None, workspace: torch.Tensor | None = None, stream=None):
+    """Deposit a list of independent boxes [(pos, nc[, out]), ...] in one launch.
+
+    Every box uses the same box side and total mass.  Returns the list of
+    output grids (float32).
+    """
+    L = lib()
+    _bind_batched(L)
+    arr, outs = _box_array(boxes, box, mass, flags)
+    o = _options(flags, stats, tuning)
+    nbytes = C.c_size_t(0)
+    _check(L.psd_batched_workspace_size(arr, len(arr), C.byref(o), C.byref(nbytes)),
+           "psd_batched_workspace_size")
+    dev = outs[0].device
+    if workspace is None:
+        workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=dev)
+    if mass_sums is not None and (mass_sums.dtype != torch.float64 or mass_sums.numel() < len(arr)):
+        raise ValueError("mass_sums must be float64 with one entry per box")
+    _check(L.psd_deposit_batched(arr, len(arr), mass_sums.data_ptr() if mass_sums is not None else None,
+                                 C.byref(o), workspace.data_ptr(), workspace.numel(),
+                                 _stream_handle(stream)),
+           "psd_deposit_batched")
+    return outs
+
+
+def autotune_batched(boxes, box: float = 1.0, mass: float = 1.0, flags: int = 0,
+                     cache_path: str | None = None, stream=None):
+    """Best launch shape for this batch (timed on the GPU; cached when cache_path is set).
+
+    Returns ((lds_cap, waves_per_cu, ordered), milliseconds).
+    """
+    L = lib()
+    _bind_batched(L)
+    arr, outs = _box_array(boxes, box, mass, flags)
+    o = _options(flags, None, (0, 0, 1))
+    nbytes = C.c_size_t(0)
+    _check(L.psd_batched_workspace_size(arr, len(arr), C.byref(o), C.byref(nbytes)),
+           "psd_batched_workspace_size")
+    ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=outs[0].device)
+    o2 = _options(flags, None, None)
+    best = Tuning()
+    ms = C.c_double(0.0)
+    _check(L.psd_autotune_batched(arr, len(arr), C.byref(o2), ws.data_ptr(), ws.numel(),
+                                  _stream_handle(stream),
+                                  cache_path.encode() if cache_path else None, C.byref(best),
+                                  C.byref(ms)),
+           "psd_autotune_batched")
+    return (best.lds_cap, best.waves_per_cu, best.ordered), float(ms.value)

@@ -7,6 +7,15 @@
 #include "psd.h"
 #include "psd_internal.h"
 
+namespace psd {
+hipError_t launch_batched(const psd_box* boxes, int n, double* mass_sums, bool density,
+                          bool accumulate, const Tuning& tune, void* ws, size_t ws_bytes,
+                          unsigned long long* stats, hipStream_t stream);
+size_t batched_ws_bytes(const psd_box* boxes, int n, bool ordered);
+hipError_t autotune_batched(const psd_box* boxes, int n, uint32_t flags, void* ws, size_t ws_bytes,
+                            hipStream_t stream, const char* cache_path, Tuning& best, double& best_ms);
+}  // namespace psd
+
 namespace {
 
 thread_local char g_detail[256] = "";
@@ -42,7 +51,32 @@ bool grid_ok(const int32_t nc[3])
     return (double)nc[0] * nc[1] * nc[2] < 9.0e15;
 }
 
-constexpr size_t kUniformWorkspace = 256;
+psd::Tuning tuning_from(const psd_options* opt)
+{
+    psd::Tuning t = psd::default_tuning();
+    if (opt && opt->tuning) {
+        const psd_tuning* u = opt->tuning;
+        if (u->lds_cap > 0) t.cap = u->lds_cap;
+        if (u->waves_per_cu > 0) t.waves_per_cu = u->waves_per_cu;
+        t.ordered = u->ordered ? 1 : 0;
+    }
+    return t;
+}
+
+bool tuning_ok(const psd_options* opt)
+{
+    if (!opt || !opt->tuning) return true;
+    const psd_tuning* u = opt->tuning;
+    return (u->lds_cap == 0 || u->lds_cap == 512 || u->lds_cap == 1024 || u->lds_cap == 2048) &&
+           u->waves_per_cu >= 0 && u->waves_per_cu <= 64 && u->reserved == 0;
+}
+
+size_t uniform_ws_bytes(const psd_particles* p, const psd_options* opt)
+{
+    const int64_t ntet = 6 * (int64_t)p->np[0] * p->np[1] * p->np[2];
+    const bool ordered = tuning_from(opt).ordered != 0;
+    return psd::queue_workspace_bytes((ntet + 63) / 64, 1, ordered);
+}
 
 bool octree_params_ok(const psd_octree_params* op)
 {
@@ -98,7 +132,8 @@ psd_status psd_uniform_workspace_size(const psd_particles* p, const int32_t nc[3
     if (!particles_ok(p)) return fail(PSD_ERR_ARG, "bad particle description");
     if (!grid_ok(nc)) return fail(PSD_ERR_ARG, "bad grid size");
     if (opt && (opt->flags & ~kUniformFlags)) return fail(PSD_ERR_UNSUPPORTED, "unknown flags");
-    *bytes = kUniformWorkspace;
+    if (!tuning_ok(opt)) return fail(PSD_ERR_ARG, "bad tuning");
+    *bytes = uniform_ws_bytes(p, opt);
     return PSD_OK;
 }
 
@@ -111,7 +146,8 @@ psd_status psd_deposit_uniform(const float* pos, const psd_particles* p, const i
     if (!grid_ok(nc)) return fail(PSD_ERR_ARG, "bad grid size");
     const uint32_t flags = opt ? opt->flags : 0u;
     if (flags & ~kUniformFlags) return fail(PSD_ERR_UNSUPPORTED, "unknown flags");
-    if (!ws || ws_bytes < kUniformWorkspace) return fail(PSD_ERR_WORKSPACE, "workspace too small");
+    if (!tuning_ok(opt)) return fail(PSD_ERR_ARG, "bad tuning");
+    if (!ws || ws_bytes < uniform_ws_bytes(p, opt)) return fail(PSD_ERR_WORKSPACE, "workspace too small");
 
     psd::UniformArgs A;
     memset(&A, 0, sizeof(A));
@@ -132,9 +168,72 @@ psd_status psd_deposit_uniform(const float* pos, const psd_particles* p, const i
     A.grid_limit = 256 * 32;
     hipError_t e = psd::launch_deposit_uniform(A, (flags & PSD_PREC_FP64) != 0,
                                                (flags & PSD_ACCUMULATE) != 0,
-                                               (flags & PSD_METHOD_CELL) != 0,
-                                               reinterpret_cast<hipStream_t>(stream));
+                                               (flags & PSD_METHOD_CELL) != 0, tuning_from(opt), ws,
+                                               ws_bytes, reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) return fail_hip(e, "deposit_uniform launch");
+    return PSD_OK;
+}
+
+static bool boxes_ok(const psd_box* boxes, int32_t n)
+{
+    if (!boxes || n < 1 || n > (1 << 20)) return false;
+    for (int32_t b = 0; b < n; ++b)
+        if (!boxes[b].pos || !boxes[b].out || !particles_ok(&boxes[b].p) || !grid_ok(boxes[b].nc))
+            return false;
+    return true;
+}
+
+static const uint32_t kBatchedFlags = PSD_OUT_DENSITY | PSD_ACCUMULATE;
+
+psd_status psd_batched_workspace_size(const psd_box* boxes, int32_t n_boxes,
+                                      const psd_options* opt, size_t* bytes)
+{
+    if (!bytes) return fail(PSD_ERR_ARG, "bytes is null");
+    if (!boxes_ok(boxes, n_boxes)) return fail(PSD_ERR_ARG, "bad box descriptors");
+    if (opt && (opt->flags & ~kBatchedFlags)) return fail(PSD_ERR_UNSUPPORTED, "unsupported flags");
+    if (!tuning_ok(opt)) return fail(PSD_ERR_ARG, "bad tuning");
+    *bytes = psd::batched_ws_bytes(boxes, n_boxes, tuning_from(opt).ordered != 0);
+    return PSD_OK;
+}
+
+psd_status psd_deposit_batched(const psd_box* boxes, int32_t n_boxes, double* mass_sums,
+                               const psd_options* opt, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!boxes_ok(boxes, n_boxes)) return fail(PSD_ERR_ARG, "bad box descriptors");
+    const uint32_t flags = opt ? opt->flags : 0u;
+    if (flags & ~kBatchedFlags) return fail(PSD_ERR_UNSUPPORTED, "unsupported flags");
+    if (!tuning_ok(opt)) return fail(PSD_ERR_ARG, "bad tuning");
+    const psd::Tuning t = tuning_from(opt);
+    if (!ws || ws_bytes < psd::batched_ws_bytes(boxes, n_boxes, t.ordered != 0))
+        return fail(PSD_ERR_WORKSPACE, "workspace too small");
+    hipError_t e = psd::launch_batched(boxes, n_boxes, mass_sums, (flags & PSD_OUT_DENSITY) != 0,
+                                       (flags & PSD_ACCUMULATE) != 0, t, ws, ws_bytes,
+                                       opt ? reinterpret_cast<unsigned long long*>(opt->stats) : nullptr,
+                                       reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail_hip(e, "deposit_batched launch");
+    return PSD_OK;
+}
+
+psd_status psd_autotune_batched(const psd_box* boxes, int32_t n_boxes, const psd_options* opt,
+                                void* ws, size_t ws_bytes, void* stream, const char* cache_path,
+                                psd_tuning* best, double* best_ms)
+{
+    if (!best) return fail(PSD_ERR_ARG, "best is null");
+    if (!boxes_ok(boxes, n_boxes)) return fail(PSD_ERR_ARG, "bad box descriptors");
+    const uint32_t flags = opt ? opt->flags : 0u;
+    if (flags & ~kBatchedFlags) return fail(PSD_ERR_UNSUPPORTED, "unsupported flags");
+    if (!ws || ws_bytes < psd::batched_ws_bytes(boxes, n_boxes, true))
+        return fail(PSD_ERR_WORKSPACE, "workspace too small (size it for ordered chunks)");
+    psd::Tuning t;
+    double ms = 0.0;
+    hipError_t e = psd::autotune_batched(boxes, n_boxes, flags & PSD_OUT_DENSITY, ws, ws_bytes,
+                                         reinterpret_cast<hipStream_t>(stream), cache_path, t, ms);
+    if (e != hipSuccess) return fail_hip(e, "autotune_batched");
+    best->lds_cap = t.cap;
+    best->waves_per_cu = t.waves_per_cu;
+    best->ordered = t.ordered;
+    best->reserved = 0;
+    if (best_ms) *best_ms = ms;
     return PSD_OK;
 }
 
@@ -144,7 +243,8 @@ psd_status psd_octree_workspace_size(const psd_particles* p, const psd_octree_pa
     if (!bytes) return fail(PSD_ERR_ARG, "bytes is null");
     if (!particles_ok(p)) return fail(PSD_ERR_ARG, "bad particle description");
     if (!octree_params_ok(op)) return fail(PSD_ERR_ARG, "bad octree parameters");
-    *bytes = psd::octree_workspace_layout(octree_args(nullptr, p, op)).bytes;
+    const psd::OctreeArgs A = octree_args(nullptr, p, op);
+    *bytes = psd::octree_workspace_layout(A).bytes + psd::octree_queue_bytes(A);
     return PSD_OK;
 }
 
@@ -183,8 +283,9 @@ psd_status psd_deposit_octree(const float* pos, const psd_particles* p, const ps
     const uint32_t flags = opt ? opt->flags : 0u;
     if (flags & ~(uint32_t)(PSD_OUT_DENSITY | PSD_ACCUMULATE))
         return fail(PSD_ERR_UNSUPPORTED, "octree deposit supports PSD_OUT_DENSITY and PSD_ACCUMULATE");
+    if (!tuning_ok(opt)) return fail(PSD_ERR_ARG, "bad tuning");
     const psd::OctreeArgs A = octree_args(pos, p, op);
-    if (!ws || ws_bytes < psd::octree_workspace_layout(A).bytes)
+    if (!ws || ws_bytes < psd::octree_workspace_layout(A).bytes + psd::octree_queue_bytes(A))
         return fail(PSD_ERR_WORKSPACE, "workspace too small");
     psd::UniformArgs U;
     memset(&U, 0, sizeof(U));
@@ -199,8 +300,8 @@ psd_status psd_deposit_octree(const float* pos, const psd_particles* p, const ps
     U.grid_limit = 256 * 32;
     const int64_t B = op->block_cells;
     hipError_t e = psd::launch_deposit_octree(A, U, reinterpret_cast<const psd::OctNode*>(nodes),
-                                              n_nodes, n_leaves * B * B * B, ws,
-                                              (flags & PSD_ACCUMULATE) != 0,
+                                              n_nodes, n_leaves * B * B * B, ws, ws_bytes,
+                                              (flags & PSD_ACCUMULATE) != 0, tuning_from(opt),
                                               reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) return fail_hip(e, "deposit_octree launch");
     return PSD_OK;

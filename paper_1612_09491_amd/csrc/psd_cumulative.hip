@@ -9,30 +9,35 @@
 // its origin).  Each column needs T split by only two half-spaces -- with the
 // inside-mask table of Section 6.3, at most 3 x 3 pieces -- and each piece's
 // share of every z-cell follows from the exact distribution of z over a
-// tetrahedron (the fraction of a tetrahedron below a plane, evaluated from
-// its four vertex distances), which plays the role of the paper's
-// subtraction along the last axis.  A cell's volume is then the 2-D
-// difference D(i,j) - D(i-1,j) - D(i,j-1) + D(i-1,j-1).  Differences cancel,
-// so everything is FP64 (full VALU rate on gfx950).
+// tetrahedron, which plays the role of the paper's subtraction along the
+// last axis.  A cell's volume is then the 2-D difference
+// D(i,j) - D(i-1,j) - D(i,j-1) + D(i-1,j-1).  Differences cancel, so
+// everything is FP64 (full VALU rate on gfx950).
 //
-// One wavefront per workgroup.  Lanes build 64 tetrahedra into LDS; small
-// ones are batched so their D arrays share an LDS buffer; larger ones are
-// tiled.  Phase 1 spreads (tet, column) pairs over lanes, phase 2 spreads
-// (tet, cell) pairs and scatters the non-zero cell masses with global atomics.
+// Work: persistent single-wavefront workgroups pop 64-tetrahedron chunks
+// from a device counter (optionally in decreasing order of estimated cost)
+// over a table of independent boxes -- one periodic grid, the levels of an
+// octree, or a batch of uneven boxes.  Per chunk, lanes build 64 tetrahedra
+// into LDS; small ones are batched so that their D arrays share an LDS
+// buffer, larger ones are tiled.  Phase 1 spreads (tet, column) pairs over
+// lanes, phase 2 spreads (tet, cell) pairs and scatters the non-zero cell
+// masses with global atomics.
+#include <string.h>
+
+#include <vector>
+
 #include "psd_internal.h"
 
 namespace psd {
 
 namespace {
 
-constexpr int kCap = 1024;  // FP64 entries of the D buffer
-
 struct CTet {
     double vr[4][3];  // vertices relative to the bbox origin (cell units), exact
     int lo[3];        // bbox origin wrapped into [0, nc)
     int ext[3];       // bbox extent in cells
     int ncell;        // ext0 * ext1 * ext2 (0: nothing to do)
-    int ncol;         // ext0 * ext1
+    int pad;
 };
 
 // A tile of one tetrahedron's cells: x in [a0, a0+ta), y in [b0, b0+tb),
@@ -55,12 +60,13 @@ __device__ __forceinline__ int fdivi(int n, float inv_d)
 }
 
 // Tile shape for a tetrahedron whose D array exceeds the buffer:
-// (ta+1)*(tb+1)*tl <= kCap with ta, tb >= 1.
+// (ta+1)*(tb+1)*tl <= CAP with ta, tb >= 1.
+template <int CAP>
 __device__ __forceinline__ void tile_shape(const CTet& S, int& ta, int& tb, int& tl, int& ntiles)
 {
-    tl = min(S.ext[2], kCap / 4);
-    tb = min(S.ext[1], kCap / (2 * tl) - 1);
-    ta = min(S.ext[0], kCap / (tl * (tb + 1)) - 1);
+    tl = min(S.ext[2], CAP / 4);
+    tb = min(S.ext[1], CAP / (2 * tl) - 1);
+    ta = min(S.ext[0], CAP / (tl * (tb + 1)) - 1);
     ntiles = ((S.ext[0] + ta - 1) / ta) * ((S.ext[1] + tb - 1) / tb) * ((S.ext[2] + tl - 1) / tl);
 }
 
@@ -75,8 +81,8 @@ __device__ __forceinline__ int wrap_add(int base, int off, int n)
 }
 
 // Output index of grid cell (x,y,z) (wrapped into [0,nc)), or -1 when the
-// cell belongs to no leaf of this level.
-__device__ __forceinline__ int64_t out_index(const UniformArgs& P, int x, int y, int z)
+// cell belongs to no leaf of this octree level.
+__device__ __forceinline__ int64_t out_index(const BoxDesc& P, int x, int y, int z)
 {
     if (!P.leaf_map) return ((int64_t)x * P.nc[1] + y) * P.nc[2] + z;
     const int B = P.leaf_block, side = P.leaf_side;
@@ -88,7 +94,7 @@ __device__ __forceinline__ int64_t out_index(const UniformArgs& P, int x, int y,
 
 // Does the wrapped box [lo, lo+ext) meet a leaf of this level?  Boxes wider
 // than a few nodes are not tested (they are simply processed).
-__device__ __forceinline__ bool touches_leaf(const UniformArgs& P, const int lo[3], const int ext[3])
+__device__ __forceinline__ bool touches_leaf(const BoxDesc& P, const int lo[3], const int ext[3])
 {
     const int B = P.leaf_block, side = P.leaf_side;
     int n0[3], nn[3];
@@ -267,93 +273,134 @@ __device__ __forceinline__ void column(const CTet& S, int a, int b, const Tile& 
     }
 }
 
+
+// Index of the box holding global chunk g (boxes sorted by chunk_begin).
+__device__ __forceinline__ int box_of(const QueueArgs& Q, int64_t g)
+{
+    if (!Q.boxes) return 0;
+    int lo = 0, hi = Q.n_boxes - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (Q.boxes[mid].chunk_begin <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Builds tetrahedron `tid` of box P into slot S; returns its bbox cell count
+// (0 when nothing is left to do) and deposits the cases that need no walk.
 template <typename OutT>
-__global__ __launch_bounds__(kWave) void deposit_cumulative_kernel(UniformArgs P)
+__device__ __forceinline__ int setup_tet(const BoxDesc& P, int64_t tid, CTet& S, double& macc,
+                                         unsigned long long& n_pair, unsigned long long& n_nz,
+                                         unsigned long long& n_inv, unsigned long long& n_deg)
+{
+    const int64_t cube = tid / 6;
+    const int p = (int)(tid - cube * 6);
+    const int64_t kk = cube % P.np[2];
+    const int64_t jj = (cube / P.np[2]) % P.np[1];
+    const int64_t ii = cube / ((int64_t)P.np[1] * P.np[2]);
+    Tet64 T;
+    make_tet(P.pos, P.np[0], P.np[1], P.np[2], P.scale, P.nc, ii, jj, kk, p, T);
+    OutT* out = reinterpret_cast<OutT*>(P.out);
+    if ((double)kuhn_sign(p) * T.D < 0.0) ++n_inv;
+    if (!(isfinite(T.D) && isfinite(T.l3))) return 0;  // non-finite input: dropped
+    if (fabs(T.D) <= 1e-12 * T.l3) {
+        // zero-volume tetrahedron: all mass to the centroid's cell
+        ++n_deg;
+        int g[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double x = 0.25 * (T.v[0][c] + T.v[1][c] + T.v[2][c] + T.v[3][c]);
+            const double fl = floor(x);
+            const double n = (double)P.nc[c];
+            g[c] = (int)(fl - n * floor(fl / n));
+        }
+        const int64_t idx = out_index(P, g[0], g[1], g[2]);
+        if (idx >= 0) {
+            ++n_nz;
+            atomicAdd(out + idx, (OutT)(P.m * P.out_scale));
+            macc += P.m;
+        }
+        return 0;
+    }
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double mn = fmin(fmin(T.v[0][c], T.v[1][c]), fmin(T.v[2][c], T.v[3][c]));
+        const double mx = fmax(fmax(T.v[0][c], T.v[1][c]), fmax(T.v[2][c], T.v[3][c]));
+        const double lo = floor(mn);
+        const int e = (int)(floor(mx) - lo) + 1;
+        // minimum-image offsets bound the extent by nc + 1 cells
+        ok = ok && e >= 1 && e <= P.nc[c] + 1;
+        const double n = (double)P.nc[c];
+        S.lo[c] = (int)(lo - n * floor(lo / n));
+        S.ext[c] = e;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) S.vr[q][c] = T.v[q][c] - lo;
+    }
+    int ncell = ok ? S.ext[0] * S.ext[1] * S.ext[2] : 0;
+    if (ncell && P.leaf_map && !touches_leaf(P, S.lo, S.ext)) ncell = 0;
+    if (ncell == 1) {
+        // the tetrahedron lies inside one cell
+        ++n_pair;
+        const int64_t idx = out_index(P, S.lo[0], S.lo[1], S.lo[2]);
+        if (idx >= 0) {
+            ++n_nz;
+            atomicAdd(out + idx, (OutT)(P.m * P.out_scale));
+            macc += P.m;
+        }
+        ncell = 0;
+    }
+    return ncell;
+}
+
+__device__ __forceinline__ void flush_mass(const BoxDesc& P, double& macc)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) macc += __shfl_xor(macc, off, kWave);
+    if (threadIdx.x == 0 && P.mass_sum && macc != 0.0) atomicAdd(P.mass_sum, macc);
+    macc = 0.0;
+}
+
+template <typename OutT, int CAP>
+__global__ __launch_bounds__(kWave) void queue_kernel(QueueArgs Q)
 {
     __shared__ CTet slots[kWave];
-    __shared__ double Dbuf[kCap];
+    __shared__ double Dbuf[CAP];
     __shared__ Tile tiles[kWave];
     __shared__ int t_slot[kWave];
     __shared__ int64_t s_incl[kWave];
+    __shared__ int64_t s_item;
 
-    if (P.level_has_leaf && *P.level_has_leaf == 0) return;
-    OutT* out = reinterpret_cast<OutT*>(P.out);
     const int lane = threadIdx.x;
-    const double sc[3] = {P.scale[0], P.scale[1], P.scale[2]};
     double macc = 0.0;
     unsigned long long n_tet = 0, n_pair = 0, n_col = 0, n_nz = 0, n_inv = 0, n_deg = 0;
+    int cur_box = -1;
+    BoxDesc P = Q.box0;
 
-    for (int64_t chunk = blockIdx.x; chunk * kWave < P.ntet; chunk += gridDim.x) {
-        const int64_t tid = chunk * kWave + lane;
+    for (;;) {
+        if (lane == 0) s_item = (int64_t)atomicAdd(Q.next, 1ull);
+        __syncthreads();
+        const int64_t item = s_item;
+        __syncthreads();
+        if (item >= Q.n_chunks) break;
+        const int64_t g = Q.order ? Q.order[item] : item;
+        const int bi = box_of(Q, g);
+        if (bi != cur_box) {
+            if (cur_box >= 0) flush_mass(P, macc);
+            cur_box = bi;
+            if (Q.boxes) P = Q.boxes[bi];
+        }
+        if (P.level_has_leaf && *P.level_has_leaf == 0) continue;
+        OutT* out = reinterpret_cast<OutT*>(P.out);
+
+        const int64_t tid = (g - P.chunk_begin) * kWave + lane;
         int ncell = 0;
         if (tid < P.ntet) {
-            const int64_t cube = tid / 6;
-            const int p = (int)(tid - cube * 6);
-            const int64_t kk = cube % P.np[2];
-            const int64_t jj = (cube / P.np[2]) % P.np[1];
-            const int64_t ii = cube / ((int64_t)P.np[1] * P.np[2]);
-            Tet64 T;
-            make_tet(P.pos, P.np[0], P.np[1], P.np[2], sc, P.nc, ii, jj, kk, p, T);
             ++n_tet;
-            if ((double)kuhn_sign(p) * T.D < 0.0) ++n_inv;
-            const bool finite_tet = isfinite(T.D) && isfinite(T.l3);
-            if (!finite_tet) {
-                // non-finite input cannot be placed; the tetrahedron is dropped
-            } else if (fabs(T.D) <= 1e-12 * T.l3) {
-                // zero-volume tetrahedron: all mass to the centroid's cell
-                ++n_deg;
-                ++n_nz;
-                int g[3];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const double x = 0.25 * (T.v[0][c] + T.v[1][c] + T.v[2][c] + T.v[3][c]);
-                    const double fl = floor(x);
-                    const double n = (double)P.nc[c];
-                    g[c] = (int)(fl - n * floor(fl / n));
-                }
-                const int64_t idx = out_index(P, g[0], g[1], g[2]);
-                if (idx >= 0) {
-                    atomicAdd(out + idx, (OutT)(P.m * P.out_scale));
-                    macc += P.m;
-                }
-            } else {
-                CTet& S = slots[lane];
-                bool ok = true;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const double mn = fmin(fmin(T.v[0][c], T.v[1][c]), fmin(T.v[2][c], T.v[3][c]));
-                    const double mx = fmax(fmax(T.v[0][c], T.v[1][c]), fmax(T.v[2][c], T.v[3][c]));
-                    const double lo = floor(mn);
-                    const int e = (int)(floor(mx) - lo) + 1;
-                    ok = ok && e >= 1 && e <= P.nc[c] + 1;
-                    const double n = (double)P.nc[c];
-                    S.lo[c] = (int)(lo - n * floor(lo / n));
-                    S.ext[c] = e;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) S.vr[q][c] = T.v[q][c] - lo;
-                }
-                ncell = ok ? S.ext[0] * S.ext[1] * S.ext[2] : 0;
-                if (ncell && P.leaf_map && !touches_leaf(P, S.lo, S.ext)) ncell = 0;
-                S.ncell = ncell;
-                S.ncol = ok ? S.ext[0] * S.ext[1] : 0;
-                if (ncell == 1) {
-                    // the tetrahedron lies inside one cell
-                    ++n_pair;
-                    ++n_nz;
-                    const int64_t idx = out_index(P, S.lo[0], S.lo[1], S.lo[2]);
-                    if (idx >= 0) {
-                        atomicAdd(out + idx, (OutT)(P.m * P.out_scale));
-                        macc += P.m;
-                    }
-                    ncell = 0;
-                    S.ncell = 0;
-                }
-            }
+            ncell = setup_tet<OutT>(P, tid, slots[lane], macc, n_pair, n_nz, n_inv, n_deg);
         }
-        if (tid >= P.ntet || ncell == 0) {
-            // mark the slot empty (the record may hold a stale tetrahedron)
-            slots[lane].ncell = 0;
-        }
+        slots[lane].ncell = ncell;
         __syncthreads();
 
         // Walk the chunk's tetrahedra in tile batches that fit the D buffer.
@@ -371,12 +418,12 @@ __global__ __launch_bounds__(kWave) void deposit_cumulative_kernel(UniformArgs P
                 }
                 Tile t;
                 int ntiles = 1;
-                if (S.ncell <= kCap) {
+                if (S.ncell <= CAP) {
                     t.a0 = 0; t.ta = S.ext[0]; t.b0 = 0; t.tb = S.ext[1];
                     t.l0 = 0; t.tl = S.ext[2]; t.ha = 0; t.hb = 0;
                 } else {
                     int ta, tb, tl;
-                    tile_shape(S, ta, tb, tl, ntiles);
+                    tile_shape<CAP>(S, ta, tb, tl, ntiles);
                     const int nx = (S.ext[0] + ta - 1) / ta, ny = (S.ext[1] + tb - 1) / tb;
                     const int ix = cur_tile % nx, iy = (cur_tile / nx) % ny, iz = cur_tile / (nx * ny);
                     t.a0 = ix * ta; t.ta = min(ta, S.ext[0] - t.a0);
@@ -386,7 +433,7 @@ __global__ __launch_bounds__(kWave) void deposit_cumulative_kernel(UniformArgs P
                     t.hb = t.b0 > 0 ? 1 : 0;
                 }
                 const int ds = tile_dsize(t);
-                if (used + ds > kCap) break;  // buffer full: run this batch first
+                if (used + ds > CAP) break;  // buffer full: run this batch first
                 t.doff = used;
                 t.inv_wb = 1.0f / (float)(t.tb + t.hb);
                 t.inv_tb = 1.0f / (float)t.tb;
@@ -407,7 +454,7 @@ __global__ __launch_bounds__(kWave) void deposit_cumulative_kernel(UniformArgs P
 
             // Phase 1: (tile, column) pairs over lanes.
             {
-                int64_t c = lane < nt ? tile_cols(tiles[lane]) : 0;
+                const int64_t c = lane < nt ? tile_cols(tiles[lane]) : 0;
                 int64_t incl = c;
 #pragma unroll
                 for (int off = 1; off < kWave; off <<= 1) {
@@ -441,7 +488,7 @@ __global__ __launch_bounds__(kWave) void deposit_cumulative_kernel(UniformArgs P
             }
             // Phase 2: (tile, cell) pairs over lanes.
             {
-                int64_t c = lane < nt ? tile_cells(tiles[lane]) : 0;
+                const int64_t c = lane < nt ? tile_cells(tiles[lane]) : 0;
                 int64_t incl = c;
 #pragma unroll
                 for (int off = 1; off < kWave; off <<= 1) {
@@ -470,7 +517,6 @@ __global__ __launch_bounds__(kWave) void deposit_cumulative_kernel(UniformArgs P
                         const int j = ij - i * t.tb;
                         const int wb = t.tb + t.hb;
                         const double* D = Dbuf + t.doff;
-                        // column index of (a, b) = (t.a0 + i, t.b0 + j) in the buffer
                         const int ca = i + t.ha, cb = j + t.hb;
                         const double d11 = D[(ca * wb + cb) * t.tl + l];
                         const bool has_a = (t.a0 + i) > 0, has_b = (t.b0 + j) > 0;
@@ -481,12 +527,12 @@ __global__ __launch_bounds__(kWave) void deposit_cumulative_kernel(UniformArgs P
                         ++n_pair;
                         // differences of values up to 1 carry ~1e-16 noise: drop it
                         if (V > 4e-15) {
-                            ++n_nz;
                             const int gx = wrap_add(S.lo[0], t.a0 + i, P.nc[0]);
                             const int gy = wrap_add(S.lo[1], t.b0 + j, P.nc[1]);
                             const int gz = wrap_add(S.lo[2], t.l0 + l, P.nc[2]);
                             const int64_t gi = out_index(P, gx, gy, gz);
                             if (gi >= 0) {
+                                ++n_nz;
                                 const double mass = P.m * V;
                                 atomicAdd(out + gi, (OutT)(mass * P.out_scale));
                                 macc += mass;
@@ -499,10 +545,10 @@ __global__ __launch_bounds__(kWave) void deposit_cumulative_kernel(UniformArgs P
         }
         __syncthreads();
     }
+    if (cur_box >= 0) flush_mass(P, macc);
 
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) {
-        macc += __shfl_xor(macc, off, kWave);
         n_tet += __shfl_xor(n_tet, off, kWave);
         n_pair += __shfl_xor(n_pair, off, kWave);
         n_col += __shfl_xor(n_col, off, kWave);
@@ -510,31 +556,206 @@ __global__ __launch_bounds__(kWave) void deposit_cumulative_kernel(UniformArgs P
         n_inv += __shfl_xor(n_inv, off, kWave);
         n_deg += __shfl_xor(n_deg, off, kWave);
     }
-    if (lane == 0) {
-        if (P.mass_sum) atomicAdd(P.mass_sum, macc);
-        if (P.stats) {
-            atomicAdd(P.stats + 0, n_tet);
-            atomicAdd(P.stats + 1, n_pair);
-            atomicAdd(P.stats + 2, n_col);
-            atomicAdd(P.stats + 3, n_nz);
-            atomicAdd(P.stats + 4, n_inv);
-            atomicAdd(P.stats + 5, n_deg);
+    if (lane == 0 && Q.stats) {
+        atomicAdd(Q.stats + 0, n_tet);
+        atomicAdd(Q.stats + 1, n_pair);
+        atomicAdd(Q.stats + 2, n_col);
+        atomicAdd(Q.stats + 3, n_nz);
+        atomicAdd(Q.stats + 4, n_inv);
+        atomicAdd(Q.stats + 5, n_deg);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Ordering by estimated cost: the number of bbox cells of a chunk's
+// tetrahedra, bucketed by its base-2 logarithm; buckets run from the most to
+// the least expensive so that the longest chunks start first.
+// ---------------------------------------------------------------------------
+
+constexpr int kBuckets = 64;
+
+__global__ __launch_bounds__(kWave) void chunk_cost_kernel(QueueArgs Q, int* bucket,
+                                                           unsigned long long* hist)
+{
+    const int64_t g = blockIdx.x;
+    if (g >= Q.n_chunks) return;
+    const BoxDesc P = Q.boxes ? Q.boxes[box_of(Q, g)] : Q.box0;
+    const int64_t tid = (g - P.chunk_begin) * kWave + threadIdx.x;
+    unsigned long long cells = 0;
+    if (tid < P.ntet) {
+        const int64_t cube = tid / 6;
+        const int p = (int)(tid - cube * 6);
+        const int64_t kk = cube % P.np[2];
+        const int64_t jj = (cube / P.np[2]) % P.np[1];
+        const int64_t ii = cube / ((int64_t)P.np[1] * P.np[2]);
+        Tet64 T;
+        make_tet(P.pos, P.np[0], P.np[1], P.np[2], P.scale, P.nc, ii, jj, kk, p, T);
+        if (isfinite(T.D) && isfinite(T.l3)) {
+            unsigned long long n = 1;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double mn = fmin(fmin(T.v[0][c], T.v[1][c]), fmin(T.v[2][c], T.v[3][c]));
+                const double mx = fmax(fmax(T.v[0][c], T.v[1][c]), fmax(T.v[2][c], T.v[3][c]));
+                n *= (unsigned long long)(floor(mx) - floor(mn) + 1.0);
+            }
+            cells = n;
         }
     }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) cells += __shfl_xor(cells, off, kWave);
+    if (threadIdx.x == 0) {
+        const int b = cells ? min(kBuckets - 1, 63 - __builtin_clzll(cells)) : 0;
+        bucket[g] = b;
+        atomicAdd(hist + b, 1ull);
+    }
+}
+
+// Exclusive offsets of the buckets, most expensive first (one wavefront).
+__global__ __launch_bounds__(kWave) void bucket_offsets_kernel(unsigned long long* hist,
+                                                               unsigned long long* cursor)
+{
+    const int lane = threadIdx.x;
+    const int b = kBuckets - 1 - lane;  // descending cost
+    unsigned long long v = hist[b];
+    unsigned long long incl = v;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const unsigned long long y = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += y;
+    }
+    cursor[b] = incl - v;
+}
+
+__global__ void scatter_order_kernel(QueueArgs Q, const int* bucket, unsigned long long* cursor,
+                                     int64_t* order)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= Q.n_chunks) return;
+    const unsigned long long at = atomicAdd(cursor + bucket[g], 1ull);
+    order[at] = g;
+}
+
+template <typename T>
+__global__ void zero_kernel(T* p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = T(0);
+}
+
+struct QueueLayout {
+    size_t next, boxes, bucket, hist, cursor, order, bytes;
+};
+
+QueueLayout queue_layout(int64_t n_chunks, int n_boxes, bool ordered)
+{
+    QueueLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return at;
+    };
+    L.next = take(sizeof(unsigned long long));
+    L.boxes = take(n_boxes > 1 ? sizeof(BoxDesc) * (size_t)n_boxes : 0);
+    L.bucket = take(ordered ? sizeof(int) * (size_t)n_chunks : 0);
+    L.hist = take(ordered ? sizeof(unsigned long long) * kBuckets : 0);
+    L.cursor = take(ordered ? sizeof(unsigned long long) * kBuckets : 0);
+    L.order = take(ordered ? sizeof(int64_t) * (size_t)n_chunks : 0);
+    L.bytes = off;
+    return L;
+}
+
+template <typename OutT>
+hipError_t launch_queue_kernel(const QueueArgs& Q, int cap, int grid, hipStream_t stream)
+{
+    if (cap <= 512)
+        hipLaunchKernelGGL((queue_kernel<OutT, 512>), dim3(grid), dim3(kWave), 0, stream, Q);
+    else if (cap <= 1024)
+        hipLaunchKernelGGL((queue_kernel<OutT, 1024>), dim3(grid), dim3(kWave), 0, stream, Q);
+    else
+        hipLaunchKernelGGL((queue_kernel<OutT, 2048>), dim3(grid), dim3(kWave), 0, stream, Q);
+    return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_deposit_cumulative(const UniformArgs& P, bool out_fp64, hipStream_t stream)
+Tuning default_tuning()
 {
-    const int64_t nchunk = (P.ntet + kWave - 1) / kWave;
-    int grid = (int)(nchunk < (int64_t)P.grid_limit ? nchunk : (int64_t)P.grid_limit);
+    Tuning t;
+    t.cap = 1024;
+    t.waves_per_cu = 8;
+    t.ordered = 0;
+    return t;
+}
+
+size_t queue_workspace_bytes(int64_t n_chunks, int n_boxes, bool ordered)
+{
+    return queue_layout(n_chunks, n_boxes, ordered).bytes;
+}
+
+int64_t queue_chunks(const BoxDesc* boxes, int n_boxes)
+{
+    int64_t n = 0;
+    for (int b = 0; b < n_boxes; ++b) n += (boxes[b].ntet + kWave - 1) / kWave;
+    return n;
+}
+
+hipError_t launch_queue(const BoxDesc* boxes_in, int n_boxes, bool out_fp64, const Tuning& tune,
+                        void* ws, size_t ws_bytes, unsigned long long* stats, hipStream_t stream)
+{
+    if (n_boxes < 1) return hipErrorInvalidValue;
+    std::vector<BoxDesc> boxes(boxes_in, boxes_in + n_boxes);
+    int64_t n_chunks = 0;
+    for (int b = 0; b < n_boxes; ++b) {
+        boxes[b].chunk_begin = n_chunks;
+        n_chunks += (boxes[b].ntet + kWave - 1) / kWave;
+    }
+    const bool ordered = tune.ordered != 0;
+    const QueueLayout L = queue_layout(n_chunks, n_boxes, ordered);
+    if (ws_bytes < L.bytes) return hipErrorInvalidValue;
+    char* base = reinterpret_cast<char*>(ws);
+    QueueArgs Q;
+    memset(&Q, 0, sizeof(Q));
+    Q.box0 = boxes[0];
+    Q.n_boxes = n_boxes;
+    Q.n_chunks = n_chunks;
+    Q.next = reinterpret_cast<unsigned long long*>(base + L.next);
+    Q.stats = stats;
+    hipError_t e;
+    if (n_boxes > 1) {
+        e = hipMemcpyAsync(base + L.boxes, boxes.data(), sizeof(BoxDesc) * (size_t)n_boxes,
+                           hipMemcpyHostToDevice, stream);
+        if (e != hipSuccess) return e;
+        Q.boxes = reinterpret_cast<const BoxDesc*>(base + L.boxes);
+    }
+    hipLaunchKernelGGL(zero_kernel<unsigned long long>, dim3(1), dim3(64), 0, stream, Q.next,
+                       (int64_t)1);
+    if (n_chunks == 0) return hipGetLastError();
+    if (ordered) {
+        int* bucket = reinterpret_cast<int*>(base + L.bucket);
+        unsigned long long* hist = reinterpret_cast<unsigned long long*>(base + L.hist);
+        unsigned long long* cursor = reinterpret_cast<unsigned long long*>(base + L.cursor);
+        int64_t* order = reinterpret_cast<int64_t*>(base + L.order);
+        hipLaunchKernelGGL(zero_kernel<unsigned long long>, dim3(1), dim3(64), 0, stream, hist,
+                           (int64_t)kBuckets);
+        hipLaunchKernelGGL(chunk_cost_kernel, dim3((unsigned)n_chunks), dim3(kWave), 0, stream, Q,
+                           bucket, hist);
+        hipLaunchKernelGGL(bucket_offsets_kernel, dim3(1), dim3(kWave), 0, stream, hist, cursor);
+        hipLaunchKernelGGL(scatter_order_kernel, dim3((unsigned)((n_chunks + 255) / 256)), dim3(256),
+                           0, stream, Q, (const int*)bucket, cursor, order);
+        Q.order = order;
+    }
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+        cus = 256;
+    int64_t grid = (int64_t)cus * (tune.waves_per_cu > 0 ? tune.waves_per_cu : 8);
+    if (grid > n_chunks) grid = n_chunks;
     if (grid < 1) grid = 1;
-    if (out_fp64)
-        hipLaunchKernelGGL(deposit_cumulative_kernel<double>, dim3(grid), dim3(kWave), 0, stream, P);
-    else
-        hipLaunchKernelGGL(deposit_cumulative_kernel<float>, dim3(grid), dim3(kWave), 0, stream, P);
-    return hipGetLastError();
+    return out_fp64 ? launch_queue_kernel<double>(Q, tune.cap, (int)grid, stream)
+                    : launch_queue_kernel<float>(Q, tune.cap, (int)grid, stream);
 }
 
 }  // namespace psd

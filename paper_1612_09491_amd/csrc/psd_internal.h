@@ -30,10 +30,60 @@ struct UniformArgs {
 };
 
 // Zero-fills the output (unless accumulating) and launches the per-cell clip
-// kernel (cell_method) or the cumulative kernel.
+// kernel (cell_method) or the cumulative queue kernel.
+struct Tuning;
 hipError_t launch_deposit_uniform(const UniformArgs& P, bool fp64, bool accumulate,
-                                  bool cell_method, hipStream_t stream);
-hipError_t launch_deposit_cumulative(const UniformArgs& P, bool out_fp64, hipStream_t stream);
+                                  bool cell_method, const Tuning& tune, void* ws, size_t ws_bytes,
+                                  hipStream_t stream);
+// ---------------------------------------------------------------------------
+// Cumulative deposit over a table of independent boxes (one for a plain grid,
+// one per level for an octree, many for a batch), driven by a work queue of
+// 64-tetrahedron chunks.
+// ---------------------------------------------------------------------------
+
+struct BoxDesc {
+    const float* pos;
+    int np[3];
+    int nc[3];
+    double scale[3];           // nc_k / box
+    double m;                  // mass per tetrahedron
+    double out_scale;          // 1 for mass, cells per unit volume for density
+    void* out;                 // float (or double) grid, or leaf blocks
+    double* mass_sum;          // may be null
+    int64_t ntet;
+    int64_t chunk_begin;       // first global chunk of this box
+    const int* leaf_map;       // octree level: node -> leaf id (null: plain grid)
+    const int* level_has_leaf; // octree level: nothing to do when 0
+    int leaf_block;
+    int leaf_side;
+};
+
+struct Tuning {
+    int cap;            // FP64 entries of the per-wave LDS buffer: 512, 1024 or 2048
+    int waves_per_cu;   // persistent workgroups per compute unit
+    int ordered;        // 1: chunks in decreasing estimated cost
+};
+
+struct QueueArgs {
+    const BoxDesc* boxes;      // device table (null: use box0)
+    BoxDesc box0;              // the single box when boxes is null
+    int n_boxes;
+    int64_t n_chunks;
+    const int64_t* order;      // device, global chunk ids in processing order, or null
+    unsigned long long* next;  // device work counter, zeroed before the launch
+    unsigned long long* stats; // may be null
+};
+
+// Workspace bytes of a queued launch over n_chunks chunks and n_boxes boxes.
+size_t queue_workspace_bytes(int64_t n_chunks, int n_boxes, bool ordered);
+int64_t queue_chunks(const BoxDesc* boxes, int n_boxes);
+BoxDesc box_from_uniform(const UniformArgs& P);
+// Lays out the workspace, uploads the box table (if n_boxes > 1), orders the
+// chunks by estimated cost when asked, and launches the deposit.  `boxes` is
+// a host array.
+hipError_t launch_queue(const BoxDesc* boxes, int n_boxes, bool out_fp64, const Tuning& tune,
+                        void* ws, size_t ws_bytes, unsigned long long* stats, hipStream_t stream);
+Tuning default_tuning();
 
 // ---------------------------------------------------------------------------
 // Octree (Section 4)
@@ -73,9 +123,11 @@ OctreeWorkspace octree_workspace_layout(const OctreeArgs& A);
 // Builds the tree; synchronizes `stream`; counts_host[0..1] = nodes, leaves.
 hipError_t launch_build_octree(const OctreeArgs& A, void* ws, OctNode* nodes, int64_t capacity,
                                int64_t* counts_host, hipStream_t stream);
-// Deposits into the leaves of `nodes`; asynchronous.
+// Deposits into the leaves of `nodes`; asynchronous.  The workspace holds the
+// octree layout followed by a queue workspace of octree_queue_bytes.
+size_t octree_queue_bytes(const OctreeArgs& A);
 hipError_t launch_deposit_octree(const OctreeArgs& A, const UniformArgs& base, const OctNode* nodes,
-                                 int64_t n_nodes, int64_t n_leaf_cells, void* ws, bool accumulate,
-                                 hipStream_t stream);
+                                 int64_t n_nodes, int64_t n_leaf_cells, void* ws, size_t ws_bytes,
+                                 bool accumulate, const Tuning& tune, hipStream_t stream);
 
 }  // namespace psd

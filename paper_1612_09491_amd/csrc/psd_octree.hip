@@ -348,9 +348,17 @@ hipError_t launch_build_octree(const OctreeArgs& A, void* ws, OctNode* nodes, in
     return hipStreamSynchronize(stream);
 }
 
+size_t octree_queue_bytes(const OctreeArgs& A)
+{
+    int64_t chunks = 0;
+    const int64_t ntet = 6 * (int64_t)A.np[0] * A.np[1] * A.np[2];
+    for (int l = 0; l <= A.max_level; ++l) chunks += (ntet + kWave - 1) / kWave;
+    return queue_workspace_bytes(chunks, A.max_level + 1, true);
+}
+
 hipError_t launch_deposit_octree(const OctreeArgs& A, const UniformArgs& base, const OctNode* nodes,
-                                 int64_t n_nodes, int64_t n_leaf_cells, void* ws, bool accumulate,
-                                 hipStream_t stream)
+                                 int64_t n_nodes, int64_t n_leaf_cells, void* ws, size_t ws_bytes,
+                                 bool accumulate, const Tuning& tune, hipStream_t stream)
 {
     const OctreeWorkspace w = octree_workspace_layout(A);
     char* wsb = reinterpret_cast<char*>(ws);
@@ -376,7 +384,9 @@ hipError_t launch_deposit_octree(const OctreeArgs& A, const UniformArgs& base, c
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    for (int l = 0; l <= A.max_level; ++l) {
+    BoxDesc boxes[8];
+    const int nl = A.max_level + 1;
+    for (int l = 0; l < nl; ++l) {
         UniformArgs P = base;
         const int n = A.block << l;
         for (int c = 0; c < 3; ++c) {
@@ -388,10 +398,10 @@ hipError_t launch_deposit_octree(const OctreeArgs& A, const UniformArgs& base, c
         P.level_has_leaf = flags + l;
         P.leaf_block = A.block;
         P.leaf_side = 1 << l;
-        e = launch_deposit_cumulative(P, false, stream);
-        if (e != hipSuccess) return e;
+        boxes[l] = box_from_uniform(P);
     }
-    return hipSuccess;
+    const size_t used = w.bytes;
+    return launch_queue(boxes, nl, false, tune, wsb + used, ws_bytes - used, base.stats, stream);
 }
 
 }  // namespace psd

@@ -7,6 +7,8 @@
 // compacted (ballot + popcount prefix) into LDS queues that are clipped 64
 // at a time.  Queues are split by the expected size of the clip so that the
 // lanes of one flush follow similar paths.
+#include <string.h>
+
 #include "psd_internal.h"
 
 namespace psd {
@@ -425,8 +427,31 @@ __global__ void fill_kernel(T* p, int64_t n, T v)
 
 }  // namespace
 
+BoxDesc box_from_uniform(const UniformArgs& P)
+{
+    BoxDesc b;
+    memset(&b, 0, sizeof(b));
+    b.pos = P.pos;
+    for (int a = 0; a < 3; ++a) {
+        b.np[a] = P.np[a];
+        b.nc[a] = P.nc[a];
+        b.scale[a] = P.scale[a];
+    }
+    b.m = P.m;
+    b.out_scale = P.out_scale;
+    b.out = P.out;
+    b.mass_sum = P.mass_sum;
+    b.ntet = P.ntet;
+    b.leaf_map = P.leaf_map;
+    b.level_has_leaf = P.level_has_leaf;
+    b.leaf_block = P.leaf_block;
+    b.leaf_side = P.leaf_side;
+    return b;
+}
+
 hipError_t launch_deposit_uniform(const UniformArgs& P, bool fp64, bool accumulate,
-                                  bool cell_method, hipStream_t stream)
+                                  bool cell_method, const Tuning& tune, void* ws, size_t ws_bytes,
+                                  hipStream_t stream)
 {
     const int64_t ncell = (int64_t)P.nc[0] * P.nc[1] * P.nc[2];
     if (!accumulate) {
@@ -442,7 +467,10 @@ hipError_t launch_deposit_uniform(const UniformArgs& P, bool fp64, bool accumula
             hipLaunchKernelGGL(fill_kernel<double>, dim3(1), dim3(64), 0, stream, P.mass_sum,
                                (int64_t)1, 0.0);
     }
-    if (!cell_method) return launch_deposit_cumulative(P, fp64, stream);
+    if (!cell_method) {
+        const BoxDesc b = box_from_uniform(P);
+        return launch_queue(&b, 1, fp64, tune, ws, ws_bytes, P.stats, stream);
+    }
     const int64_t nchunk = (P.ntet + kWave - 1) / kWave;
     int grid = (int)(nchunk < (int64_t)P.grid_limit ? nchunk : (int64_t)P.grid_limit);
     if (grid < 1) grid = 1;

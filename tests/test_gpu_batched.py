@@ -1,0 +1,105 @@
+"""Batched persistent launch over uneven boxes, and its autotuner.
+
+Each box of a batch must equal its own psd_deposit_uniform call (same
+kernel, different scheduling: FP32 atomics in another order) within 1e-6
+relative L1, and the oracle within 1e-5.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from synth import batched_box_specs, zeldovich_positions
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def psd():
+    import paper_1612_09491_amd as psd
+    if not os.path.exists(psd.LIB_PATH):
+        from paper_1612_09491_amd import build
+        build.build()
+    return psd
+
+
+def _l1(a, b):
+    return float(np.abs(a - b).sum() / np.abs(b).sum())
+
+
+def _small_batch():
+    specs = [(8, 0.4, 301, 16), (12, 1.5, 302, 24), (6, 2.5, 303, 12), (16, 0.8, 304, 32),
+             (4, 0.3, 305, 8), (10, 3.0, 306, 20)]
+    return [(zeldovich_positions(n, r, seed=s), nc) for n, r, s, nc in specs]
+
+
+@pytest.mark.parametrize("tuning", [None, (512, 4, 0), (2048, 8, 1), (1024, 2, 1)])
+def test_batch_equals_single_boxes_and_oracle(psd, orc, tuning):
+    dev = torch.device("cuda:0")
+    batch = _small_batch()
+    tens = [(torch.from_numpy(p).to(dev), nc) for p, nc in batch]
+    ms = torch.zeros(len(tens), dtype=torch.float64, device=dev)
+    outs = psd.deposit_batched(tens, mass_sums=ms, tuning=tuning)
+    torch.cuda.synchronize()
+    for (p, nc), (pt, _), out, m in zip(batch, tens, outs, ms.cpu().numpy()):
+        single = psd.deposit_uniform(pt, nc).double().cpu().numpy()
+        got = out.double().cpu().numpy()
+        assert _l1(got, single) <= 1e-6
+        ref, _ = orc.deposit_uniform(p, nc)
+        assert _l1(got, ref) <= 1e-5
+        assert abs(m - 1.0) <= 1e-9
+
+
+def test_accumulate_and_density(psd):
+    dev = torch.device("cuda:0")
+    batch = _small_batch()[:3]
+    tens = [(torch.from_numpy(p).to(dev), nc) for p, nc in batch]
+    a = [o.clone() for o in psd.deposit_batched(tens)]
+    outs = [torch.full_like(o, 1e-3) for o in a]
+    psd.deposit_batched([(t[0], t[1], o) for t, o in zip(tens, outs)], flags=psd.PSD_ACCUMULATE)
+    dens = psd.deposit_batched(tens, flags=psd.PSD_OUT_DENSITY)
+    torch.cuda.synchronize()
+    for (p, nc), x, o, d in zip(batch, a, outs, dens):
+        x = x.double().cpu().numpy()
+        assert np.allclose(o.double().cpu().numpy(), 1e-3 + x, rtol=1e-6, atol=1e-10)
+        assert np.allclose(d.double().cpu().numpy() / nc ** 3, x, rtol=1e-5, atol=1e-12)
+
+
+def test_autotuner_picks_a_valid_shape_and_caches(psd, tmp_path):
+    dev = torch.device("cuda:0")
+    tens = [(torch.from_numpy(p).to(dev), nc) for p, nc in _small_batch()]
+    cache = str(tmp_path / "tune.json")
+    (cap, waves, ordered), ms = psd.autotune_batched(tens, cache_path=cache)
+    assert cap in (1024, 2048) and waves in (4, 8) and ordered in (0, 1) and ms > 0
+    data = json.load(open(cache))
+    assert len(data) == 1
+    again, ms2 = psd.autotune_batched(tens, cache_path=cache)
+    assert again == (cap, waves, ordered) and ms2 == pytest.approx(ms, rel=1e-6)
+    outs = psd.deposit_batched(tens, tuning=(cap, waves, ordered))
+    torch.cuda.synchronize()
+    assert abs(sum(float(o.double().sum()) for o in outs) - len(outs)) <= 1e-4
+
+
+def test_64_uneven_boxes_sampled(psd, orc):
+    """The 64-box batch: Np from {16,32,64,128}, grids 2 Np, rms U[0.3, 3]."""
+    dev = torch.device("cuda:0")
+    specs = batched_box_specs()
+    pos = [zeldovich_positions(s["np"], s["rms"], seed=s["seed"]) for s in specs]
+    tens = [(torch.from_numpy(p).to(dev), s["nc"]) for p, s in zip(pos, specs)]
+    ms = torch.zeros(len(tens), dtype=torch.float64, device=dev)
+    outs = psd.deposit_batched(tens, mass_sums=ms, tuning=(1024, 8, 1))
+    torch.cuda.synchronize()
+    assert np.max(np.abs(ms.cpu().numpy() - 1.0)) <= 1e-9
+    # oracle on the smallest boxes whole, and a block of the largest one
+    order = np.argsort([s["np"] for s in specs])
+    for b in order[:3]:
+        ref, _ = orc.deposit_uniform(pos[b], specs[b]["nc"])
+        assert _l1(outs[b].double().cpu().numpy(), ref) <= 1e-5
+    big = int(order[-1])
+    nc = specs[big]["nc"]
+    ref, _ = orc.deposit_uniform(pos[big], nc, region=((8, 16, 24), (16, 16, 16)))
+    blk = outs[big].double().cpu().numpy()[8:24, 16:32, 24:40]
+    assert _l1(blk, ref) <= 1e-5
