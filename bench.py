@@ -113,6 +113,9 @@ def main() -> int:
     ap.add_argument("--cpu-cubes", type=int, default=49152,
                     help="Lagrangian cubes in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 256 MiB device copy, whose FETCH_SIZE and "
+                         "WRITE_SIZE counters scale the deposit kernel's")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -170,6 +173,13 @@ def main() -> int:
     psd.deposit_uniform(pt, nc, out=scratch, stats=st, workspace=ws, stream=stream)
     torch.cuda.synchronize()
     gstats = dict(zip(psd.STAT_NAMES, (int(x) for x in st.cpu().numpy()[:6])))
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     cpu = None
     if not args.no_cpu:

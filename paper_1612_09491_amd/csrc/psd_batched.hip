@@ -192,7 +192,7 @@ hipError_t autotune_batched(const psd_box* boxes, int n, uint32_t flags, void* w
     if (e != hipSuccess) return e;
     e = hipEventCreate(&e1);
     if (e != hipSuccess) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         return e;
     }
     best = default_tuning();
@@ -221,8 +221,8 @@ hipError_t autotune_batched(const psd_box* boxes, int n, uint32_t flags, void* w
                     best = t;
                 }
             }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (e != hipSuccess) return e;
     if (cache_path) {
         std::lock_guard<std::mutex> lock(g_cache_mutex);
