@@ -16,6 +16,7 @@ from .oracle import (  # noqa: F401
     build_octree,
     deposit_octree,
     NODE_DTYPE,
+    surrogate_examples,
     TRIVIAL,
     PAPER,
 )

@@ -910,3 +910,76 @@ int orc_deposit_octree(const float* pos, const int* np, double box, double total
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Examples for the learned overlap surrogate.                              */
+/* ------------------------------------------------------------------------ */
+
+int orc_surrogate_examples(const float* pos, const int* np, double box, const int* nc,
+                           int64_t first, int64_t count, int nthreads, uint8_t* flag,
+                           float* feat, uint8_t* mask, double* frac)
+{
+    if (!pos || !np || !nc || !flag || !feat || !mask || !frac || count < 0 || first < 0)
+        return -1;
+    int64_t ncube = (int64_t)np[0] * np[1] * np[2];
+    if (first + count > ncube) return -1;
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads)
+    for (int64_t w = 0; w < count; ++w) {
+        int64_t cube = first + w;
+        int64_t i = cube / ((int64_t)np[1] * np[2]);
+        int64_t j = (cube / np[2]) % np[1];
+        int64_t k = cube % np[2];
+        double c[8][3];
+        int amb;
+        cube_corners(pos, np, box, nc, i, j, k, c, &amb);
+        for (int p = 0; p < 6; ++p) {
+            int64_t t = 6 * w + p;
+            double v[4][3];
+            kuhn_tet(c, p, v);
+            flag[t] = 0;
+            mask[t] = 0;
+            for (int q = 0; q < 12; ++q) feat[12 * t + q] = 0.0f;
+            for (int q = 0; q < 8; ++q) frac[8 * t + q] = 0.0;
+            double D = tet_det(v);
+            double l3 = 0.0;
+            for (int a = 0; a < 4; ++a)
+                for (int b = a + 1; b < 4; ++b) {
+                    double e2 = 0.0;
+                    for (int x = 0; x < 3; ++x) e2 += (v[a][x] - v[b][x]) * (v[a][x] - v[b][x]);
+                    if (e2 > l3) l3 = e2;
+                }
+            l3 = l3 * sqrt(l3);
+            if (fabs(D) <= 1e-12 * l3) continue;
+            double lo[3];
+            int span[3], ok = 1;
+            for (int x = 0; x < 3; ++x) {
+                double mn = v[0][x], mx = v[0][x];
+                for (int a = 1; a < 4; ++a) {
+                    if (v[a][x] < mn) mn = v[a][x];
+                    if (v[a][x] > mx) mx = v[a][x];
+                }
+                lo[x] = floor(mn);
+                span[x] = (int)(floor(mx) - lo[x]);
+                if (span[x] > 1) ok = 0;
+            }
+            if (!ok) continue;
+            flag[t] = 1;
+            for (int a = 0; a < 4; ++a)
+                for (int x = 0; x < 3; ++x) feat[12 * t + 3 * a + x] = (float)(v[a][x] - lo[x]);
+            double VT = fabs(D) / 6.0;
+            for (int q = 0; q < 8; ++q) {
+                int d[3] = {(q >> 2) & 1, (q >> 1) & 1, q & 1};
+                if (d[0] > span[0] || d[1] > span[1] || d[2] > span[2]) continue;
+                mask[t] |= (uint8_t)(1u << q);
+                double clo[3], chi[3];
+                for (int x = 0; x < 3; ++x) {
+                    clo[x] = lo[x] + d[x];
+                    chi[x] = clo[x] + 1.0;
+                }
+                frac[8 * t + q] = orc_clip_tet_box(&v[0][0], clo, chi) / VT;
+            }
+        }
+    }
+    return 0;
+}

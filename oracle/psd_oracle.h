@@ -108,6 +108,22 @@ int orc_deposit_octree(const float* pos, const int* np, double box, double total
                        const orc_node* nodes, int64_t n_nodes, const int64_t* leaf_sel,
                        int64_t n_sel, int mode, int nthreads, double* out, orc_counters* cnt);
 
+/* Training and test examples for the learned overlap surrogate (an addition
+ * to the paper: a network that predicts the overlap fractions |T cap C|/|T|
+ * of the cell average of Eq. (1) for small tetrahedra).  For the 6*count
+ * tetrahedra of Lagrangian cubes first .. first+count-1 (cube index
+ * (i*np1+j)*np2+k, then split permutation 0..5), written at slot
+ * 6*(cube-first)+p:
+ *   flag[t]        1 if |D| > 1e-12 l^3 and hi-lo <= 1 on every axis, with
+ *                  lo = floor(min v), hi = floor(max v) in cell units;
+ *   feat[t][4][3]  float(v - lo), vertex order of the split;
+ *   mask[t]        bit 4dx+2dy+dz set iff cell lo+(dx,dy,dz) lies in [lo,hi];
+ *   frac[t][8]     |T cap C| / |T| for the masked-in cells, 0 elsewhere.
+ * Unflagged slots are zero.  Returns 0, or -1 on bad arguments. */
+int orc_surrogate_examples(const float* pos, const int* np, double box, const int* nc,
+                           int64_t first, int64_t count, int nthreads, uint8_t* flag,
+                           float* feat, uint8_t* mask, double* frac);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,4 +13,6 @@ from .zeldovich import (  # noqa: F401
     batched_box_specs,
     workload,
     WORKLOADS,
+    TRAIN_SEED0,
+    uniform_segments,
 )

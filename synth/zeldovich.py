@@ -189,7 +189,20 @@ WORKLOADS = {
                         "block": 16, "max_level": 4, "threshold": 1 << 20},
     # 256^3 particles, rms 2.0 spacings -> 64^3 grid (most tets fit 2x2x2 cells)
     "zel256_g64": {"np": 256, "rms": 2.0, "seed": 6, "nc": 64},
+    # the same geometry (0.25 cells per spacing) at 64^3 particles -> 16^3 grid
+    "zel64_g16": {"np": 64, "rms": 2.0, "seed": 7, "nc": 16},
 }
+
+# Seeds of the boxes that supply surrogate training examples (never used for
+# evaluation, which takes the workloads' own seeds).
+TRAIN_SEED0 = 5000
+
+
+def uniform_segments(segments, seed: int) -> np.ndarray:
+    """Concatenated float32 draws U(-b, b) for segments [(count, b), ...] (initial weights)."""
+    rng = np.random.default_rng(seed)
+    return np.concatenate([rng.uniform(-b, b, size=int(n)) for n, b in segments]).astype(
+        np.float32)
 
 
 def workload(name: str, seed: int | None = None) -> tuple[np.ndarray, dict]:
