@@ -77,7 +77,7 @@ def lib():
         L.orc_surrogate_examples.restype = C.c_int
         L.orc_surrogate_examples.argtypes = [C.c_void_p, ip, C.c_double, ip, C.c_int64,
                                              C.c_int64, C.c_int, C.c_void_p, C.c_void_p,
-                                             C.c_void_p, dp]
+                                             C.c_void_p, dp, C.c_void_p]
         _lib = L
     return _lib
 
@@ -191,7 +191,8 @@ def deposit_octree(pos, nodes: np.ndarray, leaves, block: int = 16, box: float =
 def surrogate_examples(pos, nc, box: float = 1.0, first: int = 0, count: int | None = None,
                        nthreads: int = 0, compact: bool = True) -> dict:
     """Eligible tetrahedra (bbox within 2 cells per axis) of cubes first..first+count-1 with
-    their features float(v - lo), cell masks and exact overlap fractions |T cap C|/|T|.
+    their features float(v - lo), cell masks, exact overlap fractions |T cap C|/|T| and
+    bbox origins lo (wrapped into [0, nc)).
 
     compact=True keeps only the eligible ones, in canonical order (cube, then split
     permutation); "tet" holds their global tetrahedron index 6*cube + p."""
@@ -205,13 +206,14 @@ def surrogate_examples(pos, nc, box: float = 1.0, first: int = 0, count: int | N
     feat = np.zeros((n, 12), dtype=np.float32)
     mask = np.zeros(n, dtype=np.uint8)
     frac = np.zeros((n, 8), dtype=np.float64)
+    lo = np.zeros((n, 3), dtype=np.int32)
     rc = lib().orc_surrogate_examples(pos.ctypes.data, _ip(pos.shape[:3]), box, _ip(nc), first,
                                       count, nthreads, flag.ctypes.data, feat.ctypes.data,
-                                      mask.ctypes.data, _dp(frac))
+                                      mask.ctypes.data, _dp(frac), lo.ctypes.data)
     if rc != 0:
         raise ValueError("orc_surrogate_examples: bad arguments")
     tet = np.arange(6 * first, 6 * (first + count), dtype=np.int64)
-    out = {"flag": flag, "feat": feat, "mask": mask, "frac": frac, "tet": tet}
+    out = {"flag": flag, "feat": feat, "mask": mask, "frac": frac, "lo": lo, "tet": tet}
     if compact:
         keep = flag.astype(bool)
         out = {k: v[keep] for k, v in out.items() if k != "flag"}

@@ -917,7 +917,7 @@ int orc_deposit_octree(const float* pos, const int* np, double box, double total
 
 int orc_surrogate_examples(const float* pos, const int* np, double box, const int* nc,
                            int64_t first, int64_t count, int nthreads, uint8_t* flag,
-                           float* feat, uint8_t* mask, double* frac)
+                           float* feat, uint8_t* mask, double* frac, int32_t* lo_out)
 {
     if (!pos || !np || !nc || !flag || !feat || !mask || !frac || count < 0 || first < 0)
         return -1;
@@ -939,6 +939,7 @@ int orc_surrogate_examples(const float* pos, const int* np, double box, const in
             kuhn_tet(c, p, v);
             flag[t] = 0;
             mask[t] = 0;
+            if (lo_out) lo_out[3 * t] = lo_out[3 * t + 1] = lo_out[3 * t + 2] = 0;
             for (int q = 0; q < 12; ++q) feat[12 * t + q] = 0.0f;
             for (int q = 0; q < 8; ++q) frac[8 * t + q] = 0.0;
             double D = tet_det(v);
@@ -965,6 +966,9 @@ int orc_surrogate_examples(const float* pos, const int* np, double box, const in
             }
             if (!ok) continue;
             flag[t] = 1;
+            if (lo_out)
+                for (int x = 0; x < 3; ++x)
+                    lo_out[3 * t + x] = (int32_t)wrap64((int64_t)lo[x], nc[x]);
             for (int a = 0; a < 4; ++a)
                 for (int x = 0; x < 3; ++x) feat[12 * t + 3 * a + x] = (float)(v[a][x] - lo[x]);
             double VT = fabs(D) / 6.0;

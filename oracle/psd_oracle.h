@@ -118,11 +118,12 @@ int orc_deposit_octree(const float* pos, const int* np, double box, double total
  *                  lo = floor(min v), hi = floor(max v) in cell units;
  *   feat[t][4][3]  float(v - lo), vertex order of the split;
  *   mask[t]        bit 4dx+2dy+dz set iff cell lo+(dx,dy,dz) lies in [lo,hi];
- *   frac[t][8]     |T cap C| / |T| for the masked-in cells, 0 elsewhere.
+ *   frac[t][8]     |T cap C| / |T| for the masked-in cells, 0 elsewhere;
+ *   lo[t][3]       the bbox origin wrapped into [0, nc) (may be NULL).
  * Unflagged slots are zero.  Returns 0, or -1 on bad arguments. */
 int orc_surrogate_examples(const float* pos, const int* np, double box, const int* nc,
                            int64_t first, int64_t count, int nthreads, uint8_t* flag,
-                           float* feat, uint8_t* mask, double* frac);
+                           float* feat, uint8_t* mask, double* frac, int32_t* lo);
 
 #ifdef __cplusplus
 }

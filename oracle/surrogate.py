@@ -14,7 +14,14 @@ the bbox origin lo = floor(min v):
     z  =      W4 h3 + b4      W4:  8 x 64
     p  = softmax of z over the cells inside [lo, hi] (mask); 0 elsewhere
 
-Cell c = 4 dx + 2 dy + dz.  Parameters are one packed vector (LAYOUT below,
+Cell c = 4 dx + 2 dy + dz.  The network sees the tetrahedron in a canonical
+pose (canonical()): the fractions do not change when the vertices are
+listed in another order, and reflecting a straddling axis (x -> 2 - x for an
+axis whose bbox spans 2 cells) only swaps that axis's cells.  So every
+straddling axis whose vertex sum exceeds 4 (centroid beyond the middle
+plane) is reflected, the vertices are sorted lexicographically, and the
+network's output for canonical cell c' is the prediction for cell c' ^ r,
+r = the reflected axes' cell bits.  Parameters are one packed vector (LAYOUT below,
 matrices row-major [out][in]).  The matrices are used rounded to bfloat16;
 the biases stay float32.  This reference evaluates the network in float64 on
 those rounded values; training minimises the soft-label cross entropy
@@ -82,6 +89,40 @@ def mask_bits(mask: np.ndarray) -> np.ndarray:
     return ((m >> np.arange(N_OUT, dtype=np.uint8)[None, :]) & 1).astype(bool)
 
 
+AXIS_BIT = (4, 2, 1)  # cell-index bit of each axis
+
+
+def canonical(x: np.ndarray, mask: np.ndarray):
+    """Canonical pose: (features float32 [n, 12], r int [n]).
+
+    An axis a is reflected iff its bbox spans 2 cells (mask bit AXIS_BIT[a] set)
+    and ((x0 + x1) + x2) + x3 > 4 in float64 over the 4 vertices' coordinate a;
+    reflected coordinates are 2 - x in float32; the 4 vertices are then sorted
+    lexicographically by (x, y, z)."""
+    v = np.array(x, dtype=np.float32).reshape(-1, 4, 3)
+    m = np.asarray(mask, dtype=np.int64)
+    r = np.zeros(len(v), dtype=np.int64)
+    for a in range(3):
+        s = ((v[:, 0, a].astype(np.float64) + v[:, 1, a]) + v[:, 2, a]) + v[:, 3, a]
+        refl = (((m >> AXIS_BIT[a]) & 1) == 1) & (s > 4.0)
+        v[:, :, a] = np.where(refl[:, None], np.float32(2.0) - v[:, :, a], v[:, :, a])
+        r |= np.where(refl, AXIS_BIT[a], 0)
+    order = np.lexsort((v[:, :, 2], v[:, :, 1], v[:, :, 0]), axis=1)
+    v = np.take_along_axis(v, order[:, :, None], 1)
+    return v.reshape(-1, 12), r
+
+
+def to_canonical_cells(a: np.ndarray, r: np.ndarray) -> np.ndarray:
+    """Per-cell values a[n, 8] in the original order -> canonical order (c' holds c' ^ r)."""
+    idx = np.arange(N_OUT)[None, :] ^ np.asarray(r)[:, None]
+    return np.take_along_axis(np.asarray(a), idx, 1)
+
+
+def from_canonical_cells(a: np.ndarray, r: np.ndarray) -> np.ndarray:
+    """Inverse of to_canonical_cells (the map is an involution)."""
+    return to_canonical_cells(a, r)
+
+
 def silu(z):
     return z / (1.0 + np.exp(-z))
 
@@ -92,7 +133,18 @@ def silu_grad(z):
 
 
 def forward(theta: np.ndarray, x: np.ndarray, mask: np.ndarray):
-    """Probabilities p [n, 8] and the intermediates (z1..z4, h1..h3)."""
+    """Probabilities p [n, 8] (original cell order) and the intermediates of the
+    network on the canonical pose (z1..z4, h1..h3, canonical probabilities)."""
+    xc, r = canonical(x, mask)
+    pc, c = net(theta, xc, mask)
+    c["r"] = r
+    c["pc"] = pc
+    return from_canonical_cells(pc, r), c
+
+
+def net(theta: np.ndarray, x: np.ndarray, mask: np.ndarray):
+    """The network on given (canonical) features: probabilities and intermediates.
+    The cell mask is the same in both poses."""
     P = unpack(np.asarray(theta, dtype=np.float64))
     x = np.asarray(x, dtype=np.float64)
     z1 = x @ P["W1"].T + P["b1"]
@@ -120,8 +172,15 @@ def loss(theta, x, y, mask) -> float:
 
 
 def backward(theta, x, y, mask):
-    """(loss, gradient of the mean loss with respect to theta) by reverse mode."""
-    p, c = forward(theta, x, mask)
+    """(loss, gradient of the mean loss with respect to theta) by reverse mode.
+    The loss is the same in the canonical pose with the labels permuted alike."""
+    xc, r = canonical(x, mask)
+    return net_backward(theta, xc, to_canonical_cells(np.asarray(y, dtype=np.float64), r), mask)
+
+
+def net_backward(theta, x, y, mask):
+    """(loss, gradient) of the network on given (canonical) features and labels."""
+    p, c = net(theta, x, mask)
     P = c["P"]
     n = x.shape[0]
     y = np.asarray(y, dtype=np.float64)

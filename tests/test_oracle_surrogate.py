@@ -30,8 +30,13 @@ def _theta(seed=3, scale=1.0):
 def _batch(n=37, seed=4):
     rng = np.random.default_rng(seed)
     x = rng.uniform(0.0, 2.0, size=(n, 12)).astype(np.float32)
-    mask = rng.integers(1, 256, size=n).astype(np.uint8)
-    mask[:4] = [1, 0x0F, 0x33, 0xFF]
+    # bbox masks: the cells d <= span of per-axis spans in {0, 1}
+    span = rng.integers(0, 2, size=(n, 3))
+    span[:4] = [[0, 0, 0], [0, 1, 1], [1, 0, 1], [1, 1, 1]]
+    mask = np.zeros(n, dtype=np.uint8)
+    for c in range(8):
+        d = np.array([(c >> 2) & 1, (c >> 1) & 1, c & 1])
+        mask |= (np.all(d[None, :] <= span, axis=1).astype(np.uint8) << c)
     mb = S.mask_bits(mask)
     y = np.where(mb, rng.uniform(size=(n, 8)), 0.0)
     y /= y.sum(1, keepdims=True)
@@ -78,10 +83,11 @@ def test_forward_matches_torch():
     theta = S.effective(_theta())
     x, mask, y = _batch()
     p, _ = S.forward(theta, x, mask)
+    xc, r = S.canonical(x, mask)
     net = _torch_net(theta)
-    L, lp = _torch_loss(net, x, y, mask)
+    L, lp = _torch_loss(net, xc, S.to_canonical_cells(y, r), mask)
     pt = torch.exp(lp).masked_fill(~torch.from_numpy(S.mask_bits(mask)), 0.0).detach().numpy()
-    assert np.allclose(p, pt, rtol=1e-12, atol=1e-15)
+    assert np.allclose(p, S.from_canonical_cells(pt, r), rtol=1e-12, atol=1e-15)
     assert S.loss(theta, x, y, mask) == pytest.approx(float(L.detach()), rel=1e-12)
 
 
@@ -102,7 +108,8 @@ def test_backward_matches_torch_autograd():
     x, mask, y = _batch()
     L, g = S.backward(theta, x, y, mask)
     net = _torch_net(theta)
-    Lt, _ = _torch_loss(net, x, y, mask)
+    xc, r = S.canonical(x, mask)
+    Lt, _ = _torch_loss(net, xc, S.to_canonical_cells(y, r), mask)
     Lt.backward()
     gt = {}
     for k, idx in zip(range(1, 5), (0, 2, 4, 6)):
@@ -132,6 +139,62 @@ def test_backward_central_differences():
         fd.append((S.loss(tp, x, y, mask) - S.loss(tm, x, y, mask)) / (2 * h))
     fd = np.array(fd)
     assert np.linalg.norm(fd - g[idx]) <= 1e-6 * np.linalg.norm(g[idx])
+
+
+def _dyadic_tets(n=300, seed=12):
+    """Tetrahedra with coordinates k/64 in [0, 2) and the mask of their bbox cells."""
+    rng = np.random.default_rng(seed)
+    x = (rng.integers(0, 128, size=(n, 12)) / 64.0).astype(np.float32)
+    v = x.reshape(n, 4, 3)
+    lo = np.floor(v.min(1))
+    x = (v - lo[:, None, :]).reshape(n, 12).astype(np.float32)
+    span = (np.floor(v.max(1)) - lo).astype(int)
+    mask = np.zeros(n, dtype=np.uint8)
+    for c in range(8):
+        d = np.array([(c >> 2) & 1, (c >> 1) & 1, c & 1])
+        mask |= (np.all(d[None, :] <= span, axis=1).astype(np.uint8) << c)
+    return x, mask
+
+
+def test_canonical_pose_ignores_vertex_order():
+    x, mask = _dyadic_tets()
+    xc, r = S.canonical(x, mask)
+    for perm in __import__("itertools").permutations(range(4)):
+        xp = x.reshape(-1, 4, 3)[:, list(perm), :].reshape(-1, 12)
+        xq, rq = S.canonical(xp, mask)
+        assert np.array_equal(xq, xc) and np.array_equal(rq, r)
+    # sorted vertices, reflections only on straddling axes, centroid at or below the plane
+    v = xc.reshape(-1, 4, 3)
+    # coordinates are k/64 with k < 128: an exact lexicographic key in base 128
+    keys = (v[:, :, 0] * 64).astype(np.int64) * 16384 + (v[:, :, 1] * 64).astype(np.int64) * 128 + \
+        (v[:, :, 2] * 64).astype(np.int64)
+    assert np.all(np.diff(keys, axis=1) >= 0)
+    for a, bit in enumerate(S.AXIS_BIT):
+        straddle = (mask >> bit) & 1 == 1
+        assert np.all((r & bit)[~straddle] == 0)
+        assert np.all(v[straddle, :, a].astype(np.float64).sum(1) <= 4.0)
+
+
+def test_canonical_reflection_swaps_cells():
+    x, mask = _dyadic_tets(seed=13)
+    theta = S.effective(_theta())
+    p, _ = S.forward(theta, x, mask)
+    v = x.reshape(-1, 4, 3).astype(np.float64)
+    for bits in range(1, 8):
+        flip = np.array([(bits >> 2) & 1, (bits >> 1) & 1, bits & 1], dtype=bool)
+        straddle = np.stack([(mask >> b) & 1 == 1 for b in S.AXIS_BIT], 1)
+        ok = np.all(straddle | ~flip[None, :], axis=1)  # only reflect straddling axes
+        # and avoid ties at the middle plane, where either pose is canonical
+        sums = v.sum(1)
+        ok &= np.all(~flip[None, :] | (sums != 4.0), axis=1)
+        vr = np.where(flip[None, None, :], 2.0 - v, v).astype(np.float32).reshape(-1, 12)
+        xc, r = S.canonical(x[ok], mask[ok])
+        xq, rq = S.canonical(vr[ok], mask[ok])
+        assert np.array_equal(xq, xc) and np.array_equal(rq, r ^ bits)
+        pr, _ = S.forward(theta, vr[ok], mask[ok])
+        want = np.take_along_axis(p[ok], np.arange(8)[None, :] ^ bits, 1)
+        # same network inputs; only the matrix products' blocking differs with the batch
+        assert np.allclose(pr, want, rtol=1e-13, atol=1e-16), bits
 
 
 def test_adam_matches_torch():
