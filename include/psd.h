@@ -53,9 +53,15 @@ enum {
     PSD_ACCUMULATE = 1u << 1,  /* add into `out` instead of overwriting it     */
     PSD_PREC_FP64 = 1u << 2,   /* FP64 output grid (`out` is double); with
                                   PSD_METHOD_CELL also FP64 clipping          */
-    PSD_METHOD_CELL = 1u << 3  /* per-cell exact clip in cell-local FP32
+    PSD_METHOD_CELL = 1u << 3, /* per-cell exact clip in cell-local FP32
                                   coordinates (Section 6.1 loop cell by cell);
                                   default: cumulative FP64 volumes            */
+    PSD_SURROGATE = 1u << 4    /* tetrahedra whose bbox holds 2..8 cells
+                                  inside a 2x2x2 block are deposited with the
+                                  learned overlap network (psd_options.
+                                  surrogate, see the end of this header)
+                                  instead of the exact clip; default method
+                                  only                                         */
 };
 
 typedef struct {
@@ -80,8 +86,12 @@ typedef struct {
                           [0] tets, [1] (tet, bbox cell) pairs, [2] exact
                           clips (per-cell method) or bbox columns (cumulative),
                           [3] non-zero deposits, [4] inverted tets,
-                          [5] zero-volume tets, [6..7] reserved; may be NULL */
+                          [5] zero-volume tets, [6] tets deposited by the
+                          surrogate (their bbox pairs are not in [1]),
+                          [7] reserved; may be NULL                        */
     const psd_tuning* tuning; /* host, may be NULL                           */
+    const float* surrogate;   /* DEVICE float[PSD_SURROGATE_PARAMS], the
+                                 network for PSD_SURROGATE; else ignored     */
 } psd_options;
 
 /* Workspace bytes (host out) needed by psd_deposit_uniform for this problem. */
@@ -225,6 +235,75 @@ const char* psd_status_string(psd_status s);
 
 /* Detail of the last error raised on the calling host thread (thread-local). */
 const char* psd_last_error_detail(void);
+
+/* ------------------------------------------------------------------------ */
+/* Learned overlap surrogate (an addition to the paper)                       */
+/* ------------------------------------------------------------------------ */
+/*
+ * For a tetrahedron whose bounding box spans at most 2 cells per axis (lo =
+ * floor of the vertex minima, hi = floor of the maxima, hi - lo <= 1 on every
+ * axis) a network predicts the fractions |T cap C| / |T| of the cell average
+ * of Eq. (1) for the cells C = lo + (dx,dy,dz), indexed c = 4dx + 2dy + dz:
+ *   x[12] = float(v_q,a - lo_a), q = 0..3 in split order, a = 0..2
+ *   h1 = silu(W1 x + b1), h2 = silu(W2 h1 + b2), h3 = silu(W3 h2 + b3)
+ *   z = W4 h3 + b4, p = softmax of z over the cells inside [lo, hi], else 0
+ * Parameters: one float32 vector of PSD_SURROGATE_PARAMS values, in order
+ * W1[64][12], b1[64], W2[64][64], b2[64], W3[64][64], b3[64], W4[8][64],
+ * b4[8] (matrices row-major [out][in]).  The matrices are used rounded to
+ * bfloat16 (nearest even) on the matrix cores with float32 accumulation;
+ * each feature enters as two bfloat16 parts (high, residual); biases,
+ * activations' SiLU and the softmax are float32, activations are rounded to
+ * bfloat16 between layers.  In a deposit the probabilities are renormalised
+ * in FP64 and the last cell takes the residual, so each tetrahedron deposits
+ * exactly m.  Tetrahedra inside one cell and zero-volume ones stay exact.
+ */
+enum { PSD_SURROGATE_PARAMS = 9672 };
+
+/* Workspace bytes (host out) of psd_surrogate_examples over n_cubes cubes. */
+psd_status psd_surrogate_examples_workspace_size(int64_t n_cubes, size_t* bytes);
+
+/*
+ * Training or test examples: the eligible tetrahedra of Lagrangian cubes
+ * first_cube .. first_cube + n_cubes - 1 (cube id (i*np1 + j)*np2 + k,
+ * tetrahedron id 6*cube + p) with a non-zero volume and at least min_cells
+ * (1..8) cells in their bbox, in tetrahedron order, labelled with exact FP64
+ * overlap fractions (splitting of Section 6.3).
+ *   feat    DEVICE float  [capacity][12]  features as above
+ *   frac    DEVICE double [capacity][8]   |T cap C| / |T|; 0 outside [lo, hi]
+ *   mask    DEVICE uint8  [capacity]      bit c set iff cell c is inside [lo, hi]
+ *   tet_id  DEVICE int64  [capacity] or NULL
+ *   n_out   host: number of eligible tetrahedra; may exceed capacity, in which
+ *           case only the first `capacity` are written
+ * Synchronizes the stream.  Errors: PSD_ERR_ARG, PSD_ERR_WORKSPACE, PSD_ERR_HIP.
+ */
+psd_status psd_surrogate_examples(const float* pos, const psd_particles* p, const int32_t nc[3],
+                                  int64_t first_cube, int64_t n_cubes, int32_t min_cells,
+                                  float* feat, double* frac, uint8_t* mask, int64_t* tet_id,
+                                  int64_t capacity, int64_t* n_out, void* ws, size_t ws_bytes,
+                                  void* stream);
+
+/* probs[n][8] (DEVICE float) = p of the network `params` for feat[n][12] and
+ * mask[n].  Asynchronous. */
+psd_status psd_surrogate_forward(const float* params, const float* feat, const uint8_t* mask,
+                                 int64_t n, float* probs, void* stream);
+
+/*
+ * grad (DEVICE float[PSD_SURROGATE_PARAMS], overwritten) = gradient of the
+ * mean over the batch of -sum_c y_c log p_c, y = frac of the sample, with
+ * respect to the parameters (taken at the bfloat16-rounded matrices);
+ * loss (DEVICE double[1] or NULL, overwritten) = that mean.  The batch is
+ * samples idx[0..n-1] (DEVICE int64) of the example arrays, or 0..n-1 when
+ * idx is NULL.  Asynchronous.
+ */
+psd_status psd_surrogate_backward(const float* params, const float* feat, const double* frac,
+                                  const uint8_t* mask, const int64_t* idx, int64_t n, float* grad,
+                                  double* loss, void* stream);
+
+/* One Adam update (bias-corrected moments, Kingma & Ba) of params with the
+ * moment vectors m and v (DEVICE float[PSD_SURROGATE_PARAMS]); step >= 1 is
+ * the update's 1-based count.  Asynchronous. */
+psd_status psd_surrogate_adam(float* params, const float* grad, float* m, float* v, int64_t step,
+                              float lr, float beta1, float beta2, float eps, void* stream);
 
 #ifdef __cplusplus
 }

@@ -29,8 +29,12 @@ PSD_OUT_DENSITY = 1 << 0
 PSD_ACCUMULATE = 1 << 1
 PSD_PREC_FP64 = 1 << 2
 PSD_METHOD_CELL = 1 << 3
+PSD_SURROGATE = 1 << 4
 
-STAT_NAMES = ("tets", "pairs", "clips_or_columns", "nonzero", "inverted", "degenerate")
+PSD_SURROGATE_PARAMS = 9672
+
+STAT_NAMES = ("tets", "pairs", "clips_or_columns", "nonzero", "inverted", "degenerate",
+              "surrogate_tets")
 
 
 class PsdError(RuntimeError):
@@ -49,11 +53,13 @@ class Tuning(C.Structure):
 
 
 class Options(C.Structure):
-    _fields_ = [("flags", C.c_uint32), ("stats", C.c_void_p), ("tuning", C.POINTER(Tuning))]
+    _fields_ = [("flags", C.c_uint32), ("stats", C.c_void_p), ("tuning", C.POINTER(Tuning)),
+                ("surrogate", C.c_void_p)]
 
 
-def _options(flags: int, stats, tuning) -> Options:
-    o = Options(flags, stats.data_ptr() if stats is not None else None, None)
+def _options(flags: int, stats, tuning, surrogate=None) -> Options:
+    o = Options(flags, stats.data_ptr() if stats is not None else None, None,
+                surrogate.data_ptr() if surrogate is not None else None)
     if tuning is not None:
         t = Tuning(*[int(x) for x in tuning], 0) if not isinstance(tuning, Tuning) else tuning
         o._tuning_ref = t
@@ -138,13 +144,16 @@ def uniform_workspace_size(np_, nc, flags: int = 0, box: float = 1.0, mass: floa
 def deposit_uniform(pos: torch.Tensor, nc, box: float = 1.0, mass: float = 1.0, flags: int = 0,
                     out: torch.Tensor | None = None, mass_sum: torch.Tensor | None = None,
                     stats: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
-                    stream=None, tuning=None) -> torch.Tensor:
+                    stream=None, tuning=None, surrogate: torch.Tensor | None = None) -> torch.Tensor:
     """Cell masses (or densities with PSD_OUT_DENSITY) on a periodic nc grid.
 
     Returns ``out`` (float32, or float64 with PSD_PREC_FP64).  ``mass_sum``
     (float64[1]) receives the FP64 sum of deposited mass; ``stats`` (int64[8])
-    receives counters (see STAT_NAMES).  Asynchronous on the current stream.
+    receives counters (see STAT_NAMES).  With PSD_SURROGATE, ``surrogate`` is
+    the network's packed float32 parameters.  Asynchronous on the current stream.
     """
+    if surrogate is not None:
+        _check_params(surrogate)
     p = _particles(pos, box, mass)
     g = _grid3(nc)
     dtype = torch.float64 if flags & PSD_PREC_FP64 else torch.float32
@@ -159,7 +168,7 @@ def deposit_uniform(pos: torch.Tensor, nc, box: float = 1.0, mass: float = 1.0, 
         raise ValueError("mass_sum must be a CUDA float64 tensor")
     if stats is not None and (stats.dtype != torch.int64 or stats.numel() < 8 or not stats.is_cuda):
         raise ValueError("stats must be a CUDA int64 tensor with 8 entries")
-    o = _options(flags, stats, tuning)
+    o = _options(flags, stats, tuning, surrogate)
     ncs = (C.c_int32 * 3)(*g)
     _check(lib().psd_deposit_uniform(pos.data_ptr(), C.byref(p), ncs, out.data_ptr(),
                                      mass_sum.data_ptr() if mass_sum is not None else None,
@@ -397,3 +406,174 @@ def autotune_batched(boxes, box: float = 1.0, mass: float = 1.0, flags: int = 0,
                                   C.byref(ms)),
            "psd_autotune_batched")
     return (best.lds_cap, best.waves_per_cu, best.ordered), float(ms.value)
+
+
+# ---------------------------------------------------------------------------
+# Learned overlap surrogate
+# ---------------------------------------------------------------------------
+
+SURROGATE_LAYOUT = (("W1", (64, 12)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)),
+                    ("W3", (64, 64)), ("b3", (64,)), ("W4", (8, 64)), ("b4", (8,)))
+
+
+def _bind_surrogate(L):
+    if getattr(L, "_surrogate_bound", False):
+        return
+    L.psd_surrogate_examples_workspace_size.restype = C.c_int
+    L.psd_surrogate_examples_workspace_size.argtypes = [C.c_int64, C.POINTER(C.c_size_t)]
+    L.psd_surrogate_examples.restype = C.c_int
+    L.psd_surrogate_examples.argtypes = [C.c_void_p, C.POINTER(Particles), C.POINTER(C.c_int32),
+                                         C.c_int64, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p,
+                                         C.c_void_p, C.c_void_p, C.c_int64,
+                                         C.POINTER(C.c_int64), C.c_void_p, C.c_size_t,
+                                         C.c_void_p]
+    L.psd_surrogate_forward.restype = C.c_int
+    L.psd_surrogate_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                        C.c_void_p, C.c_void_p]
+    L.psd_surrogate_backward.restype = C.c_int
+    L.psd_surrogate_backward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                         C.c_void_p]
+    L.psd_surrogate_adam.restype = C.c_int
+    L.psd_surrogate_adam.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                     C.c_float, C.c_float, C.c_float, C.c_float, C.c_void_p]
+    L._surrogate_bound = True
+
+
+def _check_params(w: torch.Tensor) -> None:
+    if (not w.is_cuda or w.dtype != torch.float32 or w.numel() != PSD_SURROGATE_PARAMS or
+            not w.is_contiguous()):
+        raise ValueError(f"surrogate parameters must be a contiguous CUDA float32 tensor of "
+                         f"{PSD_SURROGATE_PARAMS} values")
+
+
+def _cuda(t: torch.Tensor, dtype, shape_tail, name: str) -> None:
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous() or tuple(t.shape[1:]) != shape_tail:
+        raise ValueError(f"{name} must be a contiguous CUDA {dtype} tensor [n, *{shape_tail}]")
+
+
+def surrogate_examples(pos: torch.Tensor, nc, box: float = 1.0, first_cube: int = 0,
+                       n_cubes: int | None = None, min_cells: int = 2,
+                       capacity: int | None = None, with_ids: bool = True, stream=None) -> dict:
+    """Eligible tetrahedra (bbox within 2 cells per axis, >= min_cells cells) of the cube
+    range with features [n,12], exact overlap fractions [n,8] (float64), cell masks [n]
+    and tetrahedron ids [n], in tetrahedron order.  Synchronizes the stream."""
+    L = lib()
+    _bind_surrogate(L)
+    p = _particles(pos, box, 1.0)
+    g = _grid3(nc)
+    ncube = int(pos.shape[0] * pos.shape[1] * pos.shape[2])
+    if n_cubes is None:
+        n_cubes = ncube - first_cube
+    if capacity is None:
+        capacity = 6 * n_cubes
+    nbytes = C.c_size_t(0)
+    _check(L.psd_surrogate_examples_workspace_size(n_cubes, C.byref(nbytes)),
+           "psd_surrogate_examples_workspace_size")
+    dev = pos.device
+    ws = torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device=dev)
+    feat = torch.empty((capacity, 12), dtype=torch.float32, device=dev)
+    frac = torch.empty((capacity, 8), dtype=torch.float64, device=dev)
+    mask = torch.empty(capacity, dtype=torch.uint8, device=dev)
+    ids = torch.empty(capacity, dtype=torch.int64, device=dev) if with_ids else None
+    n_out = C.c_int64(0)
+    ncs = (C.c_int32 * 3)(*g)
+    _check(L.psd_surrogate_examples(pos.data_ptr(), C.byref(p), ncs, first_cube, n_cubes,
+                                    min_cells, feat.data_ptr(), frac.data_ptr(), mask.data_ptr(),
+                                    ids.data_ptr() if ids is not None else None, capacity,
+                                    C.byref(n_out), ws.data_ptr(), ws.numel(),
+                                    _stream_handle(stream)),
+           "psd_surrogate_examples")
+    n = min(int(n_out.value), capacity)
+    out = {"feat": feat[:n], "frac": frac[:n], "mask": mask[:n], "found": int(n_out.value)}
+    if ids is not None:
+        out["tet"] = ids[:n]
+    return out
+
+
+def surrogate_forward(params: torch.Tensor, feat: torch.Tensor, mask: torch.Tensor,
+                      probs: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Network probabilities [n, 8] for features [n, 12] and cell masks [n]."""
+    L = lib()
+    _bind_surrogate(L)
+    _check_params(params)
+    _cuda(feat, torch.float32, (12,), "feat")
+    n = int(feat.shape[0])
+    if mask.numel() != n or mask.dtype != torch.uint8 or not mask.is_cuda:
+        raise ValueError("mask must be a CUDA uint8 tensor [n]")
+    if probs is None:
+        probs = torch.empty((n, 8), dtype=torch.float32, device=feat.device)
+    _cuda(probs, torch.float32, (8,), "probs")
+    _check(L.psd_surrogate_forward(params.data_ptr(), feat.data_ptr(), mask.data_ptr(), n,
+                                   probs.data_ptr(), _stream_handle(stream)),
+           "psd_surrogate_forward")
+    return probs
+
+
+def surrogate_backward(params: torch.Tensor, feat: torch.Tensor, frac: torch.Tensor,
+                       mask: torch.Tensor, idx: torch.Tensor | None = None,
+                       grad: torch.Tensor | None = None, loss: torch.Tensor | None = None,
+                       stream=None):
+    """(grad [9672] float32, loss [1] float64): gradient and value of the mean soft-label
+    cross entropy over the batch idx (or all samples)."""
+    L = lib()
+    _bind_surrogate(L)
+    _check_params(params)
+    _cuda(feat, torch.float32, (12,), "feat")
+    _cuda(frac, torch.float64, (8,), "frac")
+    n = int(feat.shape[0]) if idx is None else int(idx.numel())
+    if idx is not None and (idx.dtype != torch.int64 or not idx.is_cuda or not idx.is_contiguous()):
+        raise ValueError("idx must be a contiguous CUDA int64 tensor")
+    dev = feat.device
+    if grad is None:
+        grad = torch.empty(PSD_SURROGATE_PARAMS, dtype=torch.float32, device=dev)
+    _check_params(grad)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float64, device=dev)
+    _check(L.psd_surrogate_backward(params.data_ptr(), feat.data_ptr(), frac.data_ptr(),
+                                    mask.data_ptr(), idx.data_ptr() if idx is not None else None,
+                                    n, grad.data_ptr(), loss.data_ptr(), _stream_handle(stream)),
+           "psd_surrogate_backward")
+    return grad, loss
+
+
+def surrogate_adam(params: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
+                   step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+                   eps: float = 1e-8, stream=None) -> None:
+    """One Adam update of params (in place) with moments m, v."""
+    L = lib()
+    _bind_surrogate(L)
+    for t in (params, grad, m, v):
+        _check_params(t)
+    _check(L.psd_surrogate_adam(params.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(),
+                                int(step), float(lr), float(beta1), float(beta2), float(eps),
+                                _stream_handle(stream)),
+           "psd_surrogate_adam")
+
+
+def train_surrogate(params: torch.Tensor, feat: torch.Tensor, frac: torch.Tensor,
+                    mask: torch.Tensor, order, batch: int = 4096, lr: float = 1e-3,
+                    lr_final: float | None = None, state=None, stream=None) -> dict:
+    """Adam over the examples, batches taken in the given sample order (a host or device
+    int64 array; the last batch may be shorter).  The learning rate decays geometrically to
+    lr_final over the run when given.  Every step is one backward and one Adam launch.
+    Returns the optimizer state (m, v, step) with the per-step losses (device float64)."""
+    dev = feat.device
+    if state is None:
+        state = {"m": torch.zeros_like(params), "v": torch.zeros_like(params), "step": 0}
+    order_t = torch.as_tensor(order, dtype=torch.int64).to(dev)
+    n = int(order_t.numel())
+    steps = (n + batch - 1) // batch
+    losses = torch.empty(steps, dtype=torch.float64, device=dev)
+    grad = torch.empty_like(params)
+    decay = (lr_final / lr) ** (1.0 / max(steps - 1, 1)) if lr_final else 1.0
+    rate = lr
+    for s in range(steps):
+        sl = order_t[s * batch:(s + 1) * batch]
+        surrogate_backward(params, feat, frac, mask, idx=sl, grad=grad, loss=losses[s:s + 1],
+                           stream=stream)
+        state["step"] += 1
+        surrogate_adam(params, grad, state["m"], state["v"], state["step"], rate, stream=stream)
+        rate *= decay
+    state["losses"] = losses
+    return state

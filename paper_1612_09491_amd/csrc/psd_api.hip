@@ -103,7 +103,8 @@ psd::OctreeArgs octree_args(const float* pos, const psd_particles* p, const psd_
     A.threshold = op->threshold;
     return A;
 }
-constexpr uint32_t kUniformFlags = PSD_OUT_DENSITY | PSD_ACCUMULATE | PSD_PREC_FP64 | PSD_METHOD_CELL;
+constexpr uint32_t kUniformFlags =
+    PSD_OUT_DENSITY | PSD_ACCUMULATE | PSD_PREC_FP64 | PSD_METHOD_CELL | PSD_SURROGATE;
 
 }  // namespace
 
@@ -148,6 +149,11 @@ psd_status psd_deposit_uniform(const float* pos, const psd_particles* p, const i
     if (flags & ~kUniformFlags) return fail(PSD_ERR_UNSUPPORTED, "unknown flags");
     if (!tuning_ok(opt)) return fail(PSD_ERR_ARG, "bad tuning");
     if (!ws || ws_bytes < uniform_ws_bytes(p, opt)) return fail(PSD_ERR_WORKSPACE, "workspace too small");
+    if (flags & PSD_SURROGATE) {
+        if (flags & PSD_METHOD_CELL)
+            return fail(PSD_ERR_UNSUPPORTED, "PSD_SURROGATE needs the default (cumulative) method");
+        if (!opt->surrogate) return fail(PSD_ERR_ARG, "PSD_SURROGATE without parameters");
+    }
 
     psd::UniformArgs A;
     memset(&A, 0, sizeof(A));
@@ -166,6 +172,7 @@ psd_status psd_deposit_uniform(const float* pos, const psd_particles* p, const i
     A.mass_sum = mass_sum;
     A.stats = opt ? reinterpret_cast<unsigned long long*>(opt->stats) : nullptr;
     A.grid_limit = 256 * 32;
+    A.surrogate = (flags & PSD_SURROGATE) ? opt->surrogate : nullptr;
     hipError_t e = psd::launch_deposit_uniform(A, (flags & PSD_PREC_FP64) != 0,
                                                (flags & PSD_ACCUMULATE) != 0,
                                                (flags & PSD_METHOD_CELL) != 0, tuning_from(opt), ws,
@@ -304,6 +311,86 @@ psd_status psd_deposit_octree(const float* pos, const psd_particles* p, const ps
                                               (flags & PSD_ACCUMULATE) != 0, tuning_from(opt),
                                               reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) return fail_hip(e, "deposit_octree launch");
+    return PSD_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+psd_status psd_surrogate_examples_workspace_size(int64_t n_cubes, size_t* bytes)
+{
+    if (!bytes) return fail(PSD_ERR_ARG, "bytes is null");
+    if (n_cubes < 0 || n_cubes > (int64_t)1 << 40) return fail(PSD_ERR_ARG, "bad cube count");
+    *bytes = psd::example_workspace_bytes(6 * n_cubes);
+    return PSD_OK;
+}
+
+psd_status psd_surrogate_examples(const float* pos, const psd_particles* p, const int32_t nc[3],
+                                  int64_t first_cube, int64_t n_cubes, int32_t min_cells,
+                                  float* feat, double* frac, uint8_t* mask, int64_t* tet_id,
+                                  int64_t capacity, int64_t* n_out, void* ws, size_t ws_bytes,
+                                  void* stream)
+{
+    if (!pos || !n_out) return fail(PSD_ERR_ARG, "pos or n_out is null");
+    if (!particles_ok(p)) return fail(PSD_ERR_ARG, "bad particle description");
+    if (!grid_ok(nc)) return fail(PSD_ERR_ARG, "bad grid size");
+    const int64_t ncube = (int64_t)p->np[0] * p->np[1] * p->np[2];
+    if (first_cube < 0 || n_cubes < 0 || first_cube + n_cubes > ncube)
+        return fail(PSD_ERR_ARG, "cube range outside the Lagrangian grid");
+    if (min_cells < 1 || min_cells > 8) return fail(PSD_ERR_ARG, "min_cells must be 1..8");
+    if (capacity < 0 || (capacity > 0 && (!feat || !frac || !mask)))
+        return fail(PSD_ERR_ARG, "bad capacity or null output");
+    if (!ws || ws_bytes < psd::example_workspace_bytes(6 * n_cubes))
+        return fail(PSD_ERR_WORKSPACE, "workspace too small");
+    psd::UniformArgs A;
+    memset(&A, 0, sizeof(A));
+    A.pos = pos;
+    for (int a = 0; a < 3; ++a) {
+        A.np[a] = p->np[a];
+        A.nc[a] = nc[a];
+        A.scale[a] = (double)nc[a] / p->box;
+    }
+    hipError_t e = psd::launch_examples(A, first_cube, n_cubes, min_cells, feat, frac, mask, tet_id,
+                                        capacity, ws, n_out, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail_hip(e, "surrogate_examples");
+    return PSD_OK;
+}
+
+psd_status psd_surrogate_forward(const float* params, const float* feat, const uint8_t* mask,
+                                 int64_t n, float* probs, void* stream)
+{
+    if (n < 0) return fail(PSD_ERR_ARG, "negative sample count");
+    if (!params || (n > 0 && (!feat || !mask || !probs))) return fail(PSD_ERR_ARG, "null pointer");
+    hipError_t e = psd::launch_surrogate_forward(params, feat, mask, n, probs,
+                                                 reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail_hip(e, "surrogate_forward");
+    return PSD_OK;
+}
+
+psd_status psd_surrogate_backward(const float* params, const float* feat, const double* frac,
+                                  const uint8_t* mask, const int64_t* idx, int64_t n, float* grad,
+                                  double* loss, void* stream)
+{
+    if (n < 0) return fail(PSD_ERR_ARG, "negative sample count");
+    if (!params || !grad || (n > 0 && (!feat || !frac || !mask)))
+        return fail(PSD_ERR_ARG, "null pointer");
+    hipError_t e = psd::launch_surrogate_backward(params, feat, frac, mask, idx, n, grad, loss,
+                                                  reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail_hip(e, "surrogate_backward");
+    return PSD_OK;
+}
+
+psd_status psd_surrogate_adam(float* params, const float* grad, float* m, float* v, int64_t step,
+                              float lr, float beta1, float beta2, float eps, void* stream)
+{
+    if (!params || !grad || !m || !v) return fail(PSD_ERR_ARG, "null pointer");
+    if (step < 1 || !(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) ||
+        !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return fail(PSD_ERR_ARG, "bad Adam hyper-parameters");
+    hipError_t e = psd::launch_surrogate_adam(params, grad, m, v, step, lr, beta1, beta2, eps,
+                                              reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail_hip(e, "surrogate_adam");
     return PSD_OK;
 }
 

@@ -340,6 +340,8 @@ __device__ __forceinline__ int setup_tet(const BoxDesc& P, int64_t tid, CTet& S,
     }
     int ncell = ok ? S.ext[0] * S.ext[1] * S.ext[2] : 0;
     if (ncell && P.leaf_map && !touches_leaf(P, S.lo, S.ext)) ncell = 0;
+    // deposited by the learned surrogate instead
+    if (P.skip_small && ncell >= 2 && S.ext[0] <= 2 && S.ext[1] <= 2 && S.ext[2] <= 2) return 0;
     if (ncell == 1) {
         // the tetrahedron lies inside one cell
         ++n_pair;

@@ -27,6 +27,10 @@ struct UniformArgs {
     const int* level_has_leaf; // skip the launch's work when *level_has_leaf == 0
     int leaf_block;            // B
     int leaf_side;             // 2^level
+    // Learned overlap surrogate (packed float32 parameters), or null: when
+    // set, tetrahedra with a bbox of 2..8 cells inside a 2x2x2 block go to
+    // the network instead of the exact clip.
+    const float* surrogate;
 };
 
 // Zero-fills the output (unless accumulating) and launches the per-cell clip
@@ -56,6 +60,7 @@ struct BoxDesc {
     const int* level_has_leaf; // octree level: nothing to do when 0
     int leaf_block;
     int leaf_side;
+    int skip_small;            // leave bboxes of 2..8 cells within 2x2x2 to the surrogate
 };
 
 struct Tuning {
@@ -129,5 +134,27 @@ size_t octree_queue_bytes(const OctreeArgs& A);
 hipError_t launch_deposit_octree(const OctreeArgs& A, const UniformArgs& base, const OctNode* nodes,
                                  int64_t n_nodes, int64_t n_leaf_cells, void* ws, size_t ws_bytes,
                                  bool accumulate, const Tuning& tune, hipStream_t stream);
+
+// ---------------------------------------------------------------------------
+// Learned overlap surrogate
+// ---------------------------------------------------------------------------
+
+int surrogate_param_count();
+size_t example_workspace_bytes(int64_t ntet);
+// Eligible tetrahedra of cubes [first_cube, first_cube + n_cubes) with features,
+// cell masks and exact fractions, in tetrahedron order; synchronizes `stream`
+// and sets *n_out to the number found (entries beyond capacity are dropped).
+hipError_t launch_examples(const UniformArgs& P, int64_t first_cube, int64_t n_cubes, int min_cells,
+                           float* feat, double* frac, uint8_t* mask, int64_t* tet_id,
+                           int64_t capacity, void* ws, int64_t* n_out, hipStream_t stream);
+hipError_t launch_surrogate_forward(const float* w, const float* feat, const uint8_t* mask, int64_t n,
+                                    float* probs, hipStream_t stream);
+hipError_t launch_surrogate_backward(const float* w, const float* feat, const double* frac,
+                                     const uint8_t* mask, const int64_t* idx, int64_t n, float* grad,
+                                     double* loss, hipStream_t stream);
+hipError_t launch_surrogate_adam(float* w, const float* grad, float* m, float* v, int64_t step,
+                                 float lr, float beta1, float beta2, float eps, hipStream_t stream);
+// Deposits the tetrahedra the exact path leaves to the surrogate (P.surrogate set).
+hipError_t launch_surrogate_deposit(const UniformArgs& P, bool fp64, hipStream_t stream);
 
 }  // namespace psd

@@ -446,6 +446,7 @@ BoxDesc box_from_uniform(const UniformArgs& P)
     b.level_has_leaf = P.level_has_leaf;
     b.leaf_block = P.leaf_block;
     b.leaf_side = P.leaf_side;
+    b.skip_small = P.surrogate != nullptr;
     return b;
 }
 
@@ -469,8 +470,11 @@ hipError_t launch_deposit_uniform(const UniformArgs& P, bool fp64, bool accumula
     }
     if (!cell_method) {
         const BoxDesc b = box_from_uniform(P);
-        return launch_queue(&b, 1, fp64, tune, ws, ws_bytes, P.stats, stream);
+        hipError_t e = launch_queue(&b, 1, fp64, tune, ws, ws_bytes, P.stats, stream);
+        if (e != hipSuccess || !P.surrogate) return e;
+        return launch_surrogate_deposit(P, fp64, stream);
     }
+    if (P.surrogate) return hipErrorInvalidValue;
     const int64_t nchunk = (P.ntet + kWave - 1) / kWave;
     int grid = (int)(nchunk < (int64_t)P.grid_limit ? nchunk : (int64_t)P.grid_limit);
     if (grid < 1) grid = 1;
