@@ -11,7 +11,11 @@ Prints ONE JSON line.  Also reports:
                 against the chip's VALU issue rate (the path is ALU-bound);
   cpu_baseline  the FP64 oracle timed on a seeded sample of the same
                 workload on the host cores, with its sampled-block density
-                error of the GPU result.
+                error of the GPU result;
+  surrogate     the learned-surrogate path (trained weights from
+                paper_1612_09491_amd/train.py) in tets/s with its whole-grid
+                density L1 against the exact GPU grid, on this workload and on
+                256^3 -> 64^3, where most tetrahedra are eligible.
 """
 
 from __future__ import annotations
@@ -41,10 +45,15 @@ PEAK_VALU_OPS = 256 * 64 * 2.4e9
 COST = {"tet": 60, "pair": 24, "pv": 4, "cut": 9, "sub": 20, "nz": 2}
 
 
+# Sources that define the deposit kernel; traffic counters taken on another
+# version of them are not reported.
+KERNEL_SOURCES = ("psd_cumulative.hip", "psd_device.h", "psd_internal.h")
+
+
 def source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1612_09491_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in KERNEL_SOURCES:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
@@ -93,6 +102,61 @@ def cpu_baseline(pos: np.ndarray, nc: int, gpu_grid: np.ndarray | None, n_cubes:
     return out
 
 
+SURROGATE_WEIGHTS = os.path.join(ROOT, "paper_1612_09491_amd", "surrogate_zel256_g64.npy")
+
+
+def time_deposit(psd, torch, pt, nc, flags, reps, surrogate=None, out=None, ws=None):
+    """Mean wall time (ms) of `reps` deposits after one warm-up, and the last grid."""
+    stream = torch.cuda.current_stream()
+    dtype = torch.float64 if flags & psd.PSD_PREC_FP64 else torch.float32
+    if out is None:
+        out = torch.empty((nc, nc, nc), dtype=dtype, device=pt.device)
+    if ws is None:
+        ws = torch.empty(psd.uniform_workspace_size(tuple(pt.shape[:3]), nc, flags),
+                         dtype=torch.uint8, device=pt.device)
+    psd.deposit_uniform(pt, nc, flags=flags, out=out, workspace=ws, stream=stream, surrogate=surrogate)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        psd.deposit_uniform(pt, nc, flags=flags, out=out, workspace=ws, stream=stream,
+                            surrogate=surrogate)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps, out
+
+
+def rel_l1(a, b) -> float:
+    return float((a - b).abs().sum().item() / b.abs().sum().item())
+
+
+def surrogate_leg(psd, torch, pt, p, exact_grid, reps: int) -> dict | None:
+    """The surrogate path beside the exact one: tets/s and whole-grid density L1 against
+    the exact GPU grid, on the benchmark workload and on the 0.25-cells-per-spacing one."""
+    if not os.path.exists(SURROGATE_WEIGHTS):
+        return None
+    from synth import workload
+    w = torch.from_numpy(np.load(SURROGATE_WEIGHTS).astype(np.float32)).to(pt.device)
+    ntet = 6 * p["np"] ** 3
+    st = torch.zeros(8, dtype=torch.int64, device=pt.device)
+    ms, grid = time_deposit(psd, torch, pt, p["nc"], psd.PSD_SURROGATE, reps, surrogate=w)
+    psd.deposit_uniform(pt, p["nc"], flags=psd.PSD_SURROGATE, stats=st, surrogate=w)
+    out = {"weights": os.path.basename(SURROGATE_WEIGHTS),
+           WORKLOAD: {"tets_per_s": ntet / (ms / 1e3), "ms": ms,
+                      "eligible_tets": int(st[6].item()),
+                      "density_l1_vs_exact": rel_l1(grid.double(), exact_grid)}}
+    pos2, p2 = workload("zel256_g64")
+    pt2 = torch.from_numpy(pos2).to(pt.device)
+    ntet2 = 6 * p2["np"] ** 3
+    ms_x, g_x = time_deposit(psd, torch, pt2, p2["nc"], 0, reps)
+    ms_s, g_s = time_deposit(psd, torch, pt2, p2["nc"], psd.PSD_SURROGATE, reps, surrogate=w)
+    st.zero_()
+    psd.deposit_uniform(pt2, p2["nc"], flags=psd.PSD_SURROGATE, stats=st, surrogate=w)
+    out["zel256_g64"] = {"exact_tets_per_s": ntet2 / (ms_x / 1e3),
+                         "surrogate_tets_per_s": ntet2 / (ms_s / 1e3),
+                         "eligible_tets": int(st[6].item()), "tets": ntet2,
+                         "density_l1_vs_exact": rel_l1(g_s.double(), g_x.double())}
+    return out
+
+
 def load_traffic(kernel: str, workload: str) -> dict | None:
     """HBM bytes per launch from committed rocprofv3 --pmc summaries, if current."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
@@ -105,14 +169,168 @@ def load_traffic(kernel: str, workload: str) -> dict | None:
     return t
 
 
+def oracle_sample_counts(boxes, n_cubes_total: int, seed: int, nc_of) -> dict:
+    """Oracle on a seeded cube sample spread over boxes in proportion to their cubes:
+    wall time of the exact deposit (host cores) and the paper-scheme work counters."""
+    import oracle
+    oracle.build_oracle(force=False)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    rng = np.random.default_rng(seed)
+    total = sum(b.shape[0] * b.shape[1] * b.shape[2] for b in boxes)
+    dt, tets = 0.0, 0
+    pc = None
+    for i, pos in enumerate(boxes):
+        nb = pos.shape[0] * pos.shape[1] * pos.shape[2]
+        k = max(16, int(round(n_cubes_total * nb / total)))
+        k = min(k, nb)
+        cubes = np.sort(rng.choice(nb, size=k, replace=False)).astype(np.int64)
+        t0 = time.perf_counter()
+        oracle.deposit_uniform(pos, nc_of(i), cubes=cubes, mode=oracle.TRIVIAL, nthreads=threads)
+        dt += time.perf_counter() - t0
+        tets += 6 * k
+        _, c = oracle.deposit_uniform(pos, nc_of(i), cubes=cubes,
+                                      mode=oracle.TRIVIAL | oracle.PAPER, nthreads=threads)
+        # weight each box's counters by its share of all tetrahedra
+        w = nb / total / (6 * k)
+        pc = {key: (pc[key] if pc else 0.0) + v * w for key, v in c.items()}
+    return {"seconds": dt, "tets": tets, "threads": threads, "ops_per_tet":
+            algorithmic_ops_per_tet({k: v for k, v in pc.items()} | {"n_tet": 1.0})}
+
+
+def bench_octree(args, torch, psd) -> dict:
+    """Adaptive octree: 512^3 particles with clumps, 16^3-cell leaves, <= 4 levels."""
+    from synth import workload
+    dev = torch.device("cuda:0")
+    print("generating 512^3 + clumps ...", file=sys.stderr, flush=True)
+    pos, p = workload("clump512_octree")
+    ntet = 6 * p["np"] ** 3
+    pt = torch.from_numpy(pos).to(dev)
+    stream = torch.cuda.current_stream()
+    kw = dict(block=p["block"], max_level=p["max_level"], subblock=8, threshold=p["threshold"])
+    tree = psd.build_octree(pt, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        tree = psd.build_octree(pt, **kw)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3 / 3
+    nodes = tree.to_numpy()
+    levels = np.bincount(nodes["level"][nodes["leaf_id"] >= 0], minlength=p["max_level"] + 1)
+    out = torch.empty((tree.n_leaves, 16, 16, 16), dtype=torch.float32, device=dev)
+    ms = torch.zeros(1, dtype=torch.float64, device=dev)
+    ws = torch.empty(psd.octree_workspace_size(tuple(pos.shape[:3]), **kw), dtype=torch.uint8,
+                     device=dev)
+    flags = psd.PSD_OUT_DENSITY
+
+    def step():
+        psd.deposit_octree(pt, tree, flags=flags, out=out, mass_sum=ms, workspace=ws, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    kernel_ms = e0.elapsed_time(e1) / args.steps
+    finest = int(np.nonzero(levels)[0].max())
+    nc_f = p["block"] << finest
+    line = {"value": ntet / (ms_per_step / 1e3), "ms_per_step": ms_per_step,
+            "dtype": "f64",
+            "config": {"workload": "clump512_octree", "particles": p["np"] ** 3, "tets": ntet,
+                       "leaves": tree.n_leaves, "nodes": tree.n_nodes,
+                       "leaves_per_level": levels.tolist(), "block": p["block"],
+                       "threshold": p["threshold"], "build_octree_ms": build_ms,
+                       "path": "exact cumulative clipping in FP64 into 16^3 FP32 density leaves"},
+            "mass_error": abs(float(ms.item()) - 1.0)}
+    if not args.no_cpu:
+        # the finest level's cells as a uniform grid carry the same algorithmic work
+        o = oracle_sample_counts([pos], args.cpu_cubes, 12345, lambda i: nc_f)
+        line["cpu_baseline"] = {"value": o["tets"] / o["seconds"], "unit": "tets/s",
+                                "cores": o["threads"], "kind": "oracle",
+                                "sample": f"{o['tets'] // 6} random Lagrangian cubes deposited "
+                                          f"onto the finest level's {nc_f}^3 cells, "
+                                          f"{o['seconds']:.1f} s"}
+        achieved = o["ops_per_tet"] * ntet / (kernel_ms / 1e3)
+        line["roofline"] = {"bound": "alu", "achieved": achieved / 1e12,
+                            "peak": PEAK_VALU_OPS / 1e12, "unit": "Top/s",
+                            "frac": achieved / PEAK_VALU_OPS, "traffic": None,
+                            "kernel": "queue_kernel<float, 1024>", "kernel_ms": kernel_ms,
+                            "algorithmic_ops_per_tet": o["ops_per_tet"]}
+    return line
+
+
+def bench_batched(args, torch, psd) -> dict:
+    """64 independent boxes of uneven size in one persistent launch, autotuned."""
+    from synth import batched_box_specs, zeldovich_positions
+    dev = torch.device("cuda:0")
+    specs = batched_box_specs()
+    print("generating 64 boxes ...", file=sys.stderr, flush=True)
+    host = [zeldovich_positions(sp["np"], sp["rms"], sp["seed"]) for sp in specs]
+    ntet = sum(6 * sp["np"] ** 3 for sp in specs)
+    boxes = [(torch.from_numpy(h).to(dev), sp["nc"]) for h, sp in zip(host, specs)]
+    t0 = time.perf_counter()
+    best, best_ms = psd.autotune_batched(boxes)
+    tune_s = time.perf_counter() - t0
+    outs = [torch.empty((sp["nc"],) * 3, dtype=torch.float32, device=dev) for sp in specs]
+    full = [(b[0], b[1], o) for b, o in zip(boxes, outs)]
+    ms = torch.zeros(len(specs), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        psd.deposit_batched(full, mass_sums=ms, tuning=best, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    kernel_ms = e0.elapsed_time(e1) / args.steps
+    line = {"value": ntet / (ms_per_step / 1e3), "ms_per_step": ms_per_step, "dtype": "f64",
+            "config": {"workload": "batched64", "boxes": len(specs), "tets": ntet,
+                       "particles_per_box": [sp["np"] for sp in specs],
+                       "tuning": {"lds_cap": best[0], "waves_per_cu": best[1],
+                                  "ordered": best[2]},
+                       "autotune_s": tune_s,
+                       "path": "one persistent launch over 64 box descriptors, exact FP64"},
+            "mass_error": float((ms - 1.0).abs().max().item())}
+    if not args.no_cpu:
+        o = oracle_sample_counts(host, args.cpu_cubes, 12345, lambda i: specs[i]["nc"])
+        line["cpu_baseline"] = {"value": o["tets"] / o["seconds"], "unit": "tets/s",
+                                "cores": o["threads"], "kind": "oracle",
+                                "sample": f"{o['tets'] // 6} random Lagrangian cubes spread over "
+                                          f"the 64 boxes by size, {o['seconds']:.1f} s"}
+        achieved = o["ops_per_tet"] * ntet / (kernel_ms / 1e3)
+        line["roofline"] = {"bound": "alu", "achieved": achieved / 1e12,
+                            "peak": PEAK_VALU_OPS / 1e12, "unit": "Top/s",
+                            "frac": achieved / PEAK_VALU_OPS, "traffic": None,
+                            "kernel": f"queue_kernel<float, {best[0]}>", "kernel_ms": kernel_ms,
+                            "algorithmic_ops_per_tet": o["ops_per_tet"]}
+    return line
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cpu-cubes", type=int, default=49152,
+    ap.add_argument("--cpu-cubes", type=int, default=150000,
                     help="Lagrangian cubes in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
+    ap.add_argument("--workload", default=WORKLOAD,
+                    choices=[WORKLOAD, "clump512_octree", "batched64"],
+                    help="the benchmark workload (default) or a secondary one")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy, whose FETCH_SIZE and "
                          "WRITE_SIZE counters scale the deposit kernel's")
@@ -127,8 +345,17 @@ def main() -> int:
     from synth import workload
 
     if not os.path.exists(psd.LIB_PATH):
-        from paper_1612_09491_amd import build as hip_build
-        hip_build.build()
+        raise SystemExit(f"{psd.LIB_PATH} is missing: run __graft_entry__.build() first")
+
+    if args.workload != WORKLOAD:
+        fn = {"clump512_octree": bench_octree, "batched64": bench_batched}[args.workload]
+        extra = fn(args, torch, psd)
+        line = {"metric": METRIC, "unit": "tets/s", "n_gpus": 1, "steps": args.steps,
+                "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+                "vs_baseline": None, "data": "synthetic"}
+        line.update(extra)
+        print(json.dumps(line), flush=True)
+        return 0
 
     dev = torch.device("cuda:0")
     pos, p = workload(WORKLOAD)
@@ -181,6 +408,10 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
 
+    sur = None
+    if not args.no_surrogate:
+        sur = surrogate_leg(psd, torch, pt, p, out.double(), reps=max(1, min(args.steps, 3)))
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(pos, nc, grid, args.cpu_cubes)
@@ -229,6 +460,7 @@ def main() -> int:
         "gpu_counters": gstats,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "surrogate": sur,
     }
     if cpu is not None and "gpu_block_l1" in cpu:
         line["density_l1_sampled_block"] = cpu["gpu_block_l1"]
