@@ -91,8 +91,8 @@ def train(params: torch.Tensor, ex: dict, epochs: int, batch: int, lr: float, lr
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
-    ap.add_argument("--examples", type=int, default=10_000_000)
-    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--examples", type=int, default=20_000_000)
+    ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--lr-final", type=float, default=2e-5)

@@ -62,10 +62,12 @@ def test_accumulate_and_density(psd):
     psd.deposit_batched([(t[0], t[1], o) for t, o in zip(tens, outs)], flags=psd.PSD_ACCUMULATE)
     dens = psd.deposit_batched(tens, flags=psd.PSD_OUT_DENSITY)
     torch.cuda.synchronize()
+    # separate launches add their FP32 atomics in different orders: FP32 tolerance
     for (p, nc), x, o, d in zip(batch, a, outs, dens):
         x = x.double().cpu().numpy()
-        assert np.allclose(o.double().cpu().numpy(), 1e-3 + x, rtol=1e-6, atol=1e-10)
-        assert np.allclose(d.double().cpu().numpy() / nc ** 3, x, rtol=1e-5, atol=1e-12)
+        tol = 1e-5 * x.max()
+        assert np.allclose(o.double().cpu().numpy(), 1e-3 + x, rtol=1e-5, atol=tol)
+        assert np.allclose(d.double().cpu().numpy() / nc ** 3, x, rtol=1e-5, atol=tol)
 
 
 def test_autotuner_picks_a_valid_shape_and_caches(psd, tmp_path):
