@@ -129,7 +129,12 @@ struct ZDist {
     double r20, r30, r21, r31;
 };
 
-__device__ __forceinline__ double rcp_or0(double d) { return d > 0.0 ? fdiv_pos(1.0, d) : 0.0; }
+__device__ __forceinline__ double rcp_or0(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    return d > 0.0 ? r : 0.0;
+}
 
 __device__ __forceinline__ void zdist_init(const double z[4], ZDist& Z)
 {
@@ -153,19 +158,15 @@ __device__ __forceinline__ void zdist_init(const double z[4], ZDist& Z)
 
 __device__ __forceinline__ double zdist_below(const ZDist& Z, double k)
 {
-    if (k <= Z.s0) return 0.0;
-    if (k >= Z.s3) return 1.0;
-    if (k <= Z.s1) {
-        const double u = k - Z.s0;
-        return u * u * u * Z.iA;
-    }
-    if (k >= Z.s2) {
-        const double w = Z.s3 - k;
-        return 1.0 - w * w * w * Z.iC;
-    }
-    const double t02 = (k - Z.s0) * Z.r20, t03 = (k - Z.s0) * Z.r30;
-    const double t12 = (k - Z.s1) * Z.r21, t13 = (k - Z.s1) * Z.r31;
-    return t02 * t03 * (1.0 - t13) + t02 * (1.0 - t12) * t13 + t12 * t13;
+    const double u = k - Z.s0, w = Z.s3 - k, t = k - Z.s1;
+    const double lowr = u * u * u * Z.iA;
+    const double highr = 1.0 - w * w * w * Z.iC;
+    const double t02 = u * Z.r20, t03 = u * Z.r30;
+    const double t12 = t * Z.r21, t13 = t * Z.r31;
+    const double mid = t02 * t03 * (1.0 - t13) + t02 * (1.0 - t12) * t13 + t12 * t13;
+    double F = k <= Z.s1 ? lowr : (k >= Z.s2 ? highr : mid);
+    F = k >= Z.s3 ? 1.0 : F;
+    return k <= Z.s0 ? 0.0 : F;
 }
 
 // Adds frac * (share of each z-cell of the tile) for one piece.
