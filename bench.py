@@ -324,8 +324,9 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cpu-cubes", type=int, default=150000,
-                    help="Lagrangian cubes in the oracle's timed sample")
+    ap.add_argument("--cpu-cubes", type=int, default=None,
+                    help="Lagrangian cubes in the oracle's timed sample (default per workload, "
+                         "about 10-30 s of host work)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
     ap.add_argument("--workload", default=WORKLOAD,
@@ -335,6 +336,8 @@ def main() -> int:
                     help="also run one plain 256 MiB device copy, whose FETCH_SIZE and "
                          "WRITE_SIZE counters scale the deposit kernel's")
     args = ap.parse_args()
+    if args.cpu_cubes is None:
+        args.cpu_cubes = {"clump512_octree": 1_000_000}.get(args.workload, 150_000)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is described in DESIGN.md but not built.", file=sys.stderr)
