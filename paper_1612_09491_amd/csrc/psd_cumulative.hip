@@ -32,13 +32,18 @@ namespace psd {
 
 namespace {
 
+// A tetrahedron in its walk frame: axes 0 and 1 are split by the column
+// planes, axis 2 gets the exact distribution.  Axis 2 is the longest side of
+// the bbox, which makes the fewest columns for the same cells.
 struct CTet {
-    double vr[4][3];  // vertices relative to the bbox origin (cell units), exact
-    int lo[3];        // bbox origin wrapped into [0, nc)
-    int ext[3];       // bbox extent in cells
+    double vr[4][3];  // vertices relative to the bbox origin, walk-frame axes (cell units), exact
+    int lo[3];        // bbox origin wrapped into [0, nc), grid axes
+    int ext[3];       // bbox extent in cells, walk-frame axes
     int ncell;        // ext0 * ext1 * ext2 (0: nothing to do)
-    int pad;
+    int axes;         // grid axis of walk axis k in bits 2k..2k+1
 };
+
+__device__ __forceinline__ int walk_axis(const CTet& S, int k) { return (S.axes >> (2 * k)) & 3; }
 
 // A tile of one tetrahedron's cells: x in [a0, a0+ta), y in [b0, b0+tb),
 // z in [l0, l0+tl).  Its D buffer covers columns a in [a0-ha, a0+ta),
@@ -325,24 +330,37 @@ __device__ __forceinline__ int setup_tet(const BoxDesc& P, int64_t tid, CTet& S,
         return 0;
     }
     bool ok = true;
+    double lof[3];
+    int e[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const double mn = fmin(fmin(T.v[0][c], T.v[1][c]), fmin(T.v[2][c], T.v[3][c]));
         const double mx = fmax(fmax(T.v[0][c], T.v[1][c]), fmax(T.v[2][c], T.v[3][c]));
-        const double lo = floor(mn);
-        const int e = (int)(floor(mx) - lo) + 1;
+        lof[c] = floor(mn);
+        e[c] = (int)(floor(mx) - lof[c]) + 1;
         // minimum-image offsets bound the extent by nc + 1 cells
-        ok = ok && e >= 1 && e <= P.nc[c] + 1;
+        ok = ok && e[c] >= 1 && e[c] <= P.nc[c] + 1;
         const double n = (double)P.nc[c];
-        S.lo[c] = (int)(lo - n * floor(lo / n));
-        S.ext[c] = e;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) S.vr[q][c] = T.v[q][c] - lo;
+        S.lo[c] = (int)(lof[c] - n * floor(lof[c] / n));
     }
-    int ncell = ok ? S.ext[0] * S.ext[1] * S.ext[2] : 0;
-    if (ncell && P.leaf_map && !touches_leaf(P, S.lo, S.ext)) ncell = 0;
+    int ncell = ok ? e[0] * e[1] * e[2] : 0;
+    if (ncell && P.leaf_map && !touches_leaf(P, S.lo, e)) ncell = 0;
     // deposited by the learned surrogate instead
-    if (P.skip_small && ncell >= 2 && S.ext[0] <= 2 && S.ext[1] <= 2 && S.ext[2] <= 2) return 0;
+    if (P.skip_small && ncell >= 2 && e[0] <= 2 && e[1] <= 2 && e[2] <= 2) return 0;
+    // walk frame: the longest axis last (ties keep the later grid axis)
+    const int w2 = (e[0] > e[1] && e[0] > e[2]) ? 0 : (e[1] > e[2] ? 1 : 2);
+    const int w0 = w2 == 0 ? 1 : 0, w1 = w2 == 2 ? 1 : 2;
+    S.axes = w0 | (w1 << 2) | (w2 << 4);
+    const int wa[3] = {w0, w1, w2};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int c = wa[k];
+        const double lo = c == 0 ? lof[0] : (c == 1 ? lof[1] : lof[2]);
+        S.ext[k] = c == 0 ? e[0] : (c == 1 ? e[1] : e[2]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            S.vr[q][k] = (c == 0 ? T.v[q][0] : (c == 1 ? T.v[q][1] : T.v[q][2])) - lo;
+    }
     if (ncell == 1) {
         // the tetrahedron lies inside one cell
         ++n_pair;
@@ -530,9 +548,15 @@ __global__ __launch_bounds__(kWave) void queue_kernel(QueueArgs Q)
                         ++n_pair;
                         // differences of values up to 1 carry ~1e-16 noise: drop it
                         if (V > 4e-15) {
-                            const int gx = wrap_add(S.lo[0], t.a0 + i, P.nc[0]);
-                            const int gy = wrap_add(S.lo[1], t.b0 + j, P.nc[1]);
-                            const int gz = wrap_add(S.lo[2], t.l0 + l, P.nc[2]);
+                            // walk-frame offsets back to grid axes
+                            const int o0 = t.a0 + i, o1 = t.b0 + j, o2 = t.l0 + l;
+                            const int k0 = walk_axis(S, 0), k1 = walk_axis(S, 1);
+                            const int ox = k0 == 0 ? o0 : (k1 == 0 ? o1 : o2);
+                            const int oy = k0 == 1 ? o0 : (k1 == 1 ? o1 : o2);
+                            const int oz = k0 == 2 ? o0 : (k1 == 2 ? o1 : o2);
+                            const int gx = wrap_add(S.lo[0], ox, P.nc[0]);
+                            const int gy = wrap_add(S.lo[1], oy, P.nc[1]);
+                            const int gz = wrap_add(S.lo[2], oz, P.nc[2]);
                             const int64_t gi = out_index(P, gx, gy, gz);
                             if (gi >= 0) {
                                 ++n_nz;
