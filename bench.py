@@ -411,6 +411,9 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
 
+    # the same deposit into an FP64 grid (identical arithmetic, double atomics)
+    ms64, _ = time_deposit(psd, torch, pt, nc, psd.PSD_PREC_FP64, reps=max(1, min(args.steps, 2)))
+
     sur = None
     if not args.no_surrogate:
         sur = surrogate_leg(psd, torch, pt, p, out.double(), reps=max(1, min(args.steps, 3)))
@@ -464,6 +467,7 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "surrogate": sur,
+        "fp64_grid": {"tets_per_s": ntet / (ms64 / 1e3), "ms": ms64},
     }
     if cpu is not None and "gpu_block_l1" in cpu:
         line["density_l1_sampled_block"] = cpu["gpu_block_l1"]

@@ -412,7 +412,17 @@ __global__ __launch_bounds__(kWave) void queue_kernel(QueueArgs Q)
             cur_box = bi;
             if (Q.boxes) P = Q.boxes[bi];
         }
-        if (P.level_has_leaf && *P.level_has_leaf == 0) continue;
+        if (P.level_has_leaf && *P.level_has_leaf == 0) {
+            // a level without leaves: in index order its remaining chunks
+            // are skipped in one step (the counter only moves forward)
+            if (!Q.order && lane == 0) {
+                const unsigned long long end =
+                    (Q.boxes && bi + 1 < Q.n_boxes) ? (unsigned long long)Q.boxes[bi + 1].chunk_begin
+                                                    : (unsigned long long)Q.n_chunks;
+                atomicMax(Q.next, end);
+            }
+            continue;
+        }
         OutT* out = reinterpret_cast<OutT*>(P.out);
 
         const int64_t tid = (g - P.chunk_begin) * kWave + lane;
