@@ -68,7 +68,7 @@ def algorithmic_ops_per_tet(cnt: dict) -> float:
 
 
 def cpu_baseline(pos: np.ndarray, nc: int, gpu_grid: np.ndarray | None, n_cubes: int,
-                 seed: int = 12345) -> dict:
+                 seed: int = 12345, other_grids: dict | None = None) -> dict:
     """The FP64 oracle on a seeded random sample of Lagrangian cubes, on host cores."""
     import oracle
     oracle.build_oracle(force=False)
@@ -98,6 +98,9 @@ def cpu_baseline(pos: np.ndarray, nc: int, gpu_grid: np.ndarray | None, n_cubes:
         blk = gpu_grid[blo[0]:blo[0] + 16, blo[1]:blo[1] + 16, blo[2]:blo[2] + 16]
         out["gpu_block_l1"] = float(np.abs(blk - ref).sum() / np.abs(ref).sum())
         out["gpu_block"] = blo
+        for name, g in (other_grids or {}).items():
+            b2 = g[blo[0]:blo[0] + 16, blo[1]:blo[1] + 16, blo[2]:blo[2] + 16]
+            out[f"{name}_block_l1"] = float(np.abs(b2 - ref).sum() / np.abs(ref).sum())
     out["_paper_counters"] = pcnt
     return out
 
@@ -329,6 +332,8 @@ def main() -> int:
                          "about 10-30 s of host work)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
+    ap.add_argument("--no-cell", action="store_true",
+                    help="skip the per-cell (cell-local FP32) method's timing")
     ap.add_argument("--workload", default=WORKLOAD,
                     choices=[WORKLOAD, "clump512_octree", "batched64"],
                     help="the benchmark workload (default) or a secondary one")
@@ -413,6 +418,12 @@ def main() -> int:
 
     # the same deposit into an FP64 grid (identical arithmetic, double atomics)
     ms64, _ = time_deposit(psd, torch, pt, nc, psd.PSD_PREC_FP64, reps=max(1, min(args.steps, 2)))
+    # the per-cell method: cell-local FP32 clipping (one timed run)
+    ms_cell, cell_grid = (None, None)
+    if not args.no_cell:
+        ms_cell, g = time_deposit(psd, torch, pt, nc, psd.PSD_METHOD_CELL, reps=1)
+        cell_grid = g.double().cpu().numpy()
+        del g
 
     sur = None
     if not args.no_surrogate:
@@ -420,7 +431,8 @@ def main() -> int:
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(pos, nc, grid, args.cpu_cubes)
+        cpu = cpu_baseline(pos, nc, grid, args.cpu_cubes,
+                           other_grids={"fp32_cell_local": cell_grid} if cell_grid is not None else None)
 
     roofline = None
     if cpu is not None:
@@ -468,6 +480,9 @@ def main() -> int:
         "cpu_baseline": cpu,
         "surrogate": sur,
         "fp64_grid": {"tets_per_s": ntet / (ms64 / 1e3), "ms": ms64},
+        "fp32_cell_local": ({"tets_per_s": ntet / (ms_cell / 1e3), "ms": ms_cell,
+                             "block_l1": (cpu or {}).get("fp32_cell_local_block_l1")}
+                            if ms_cell else None),
     }
     if cpu is not None and "gpu_block_l1" in cpu:
         line["density_l1_sampled_block"] = cpu["gpu_block_l1"]

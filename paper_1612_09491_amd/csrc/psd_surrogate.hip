@@ -76,7 +76,7 @@ struct Net {
     bf16x8 w2[4][2];   // [unit tile][k step]
     bf16x8 w3[4][2];
     bf16x8 w4[2];      // rows 0..7 = cells, 8..15 zero
-    f32x4 b1[4], b2[4], b3[4], b4;  // bias of rows 4 (l >> 4) + 0..3 of each tile
+    const float* w;    // the packed parameters (biases are read from here, cached)
 };
 
 __device__ __forceinline__ void load_net(const float* __restrict__ w, Net& N)
@@ -99,13 +99,6 @@ __device__ __forceinline__ void load_net(const float* __restrict__ w, Net& N)
                 N.w2[mt][ks][e] = to_bf16(w[oW2 + u * kH + k]);
                 N.w3[mt][ks][e] = to_bf16(w[oW3 + u * kH + k]);
             }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int ub = mt * 16 + 4 * g + i;
-            N.b1[mt][i] = w[oB1 + ub];
-            N.b2[mt][i] = w[oB2 + ub];
-            N.b3[mt][i] = w[oB3 + ub];
-        }
     }
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks)
@@ -114,11 +107,7 @@ __device__ __forceinline__ void load_net(const float* __restrict__ w, Net& N)
             const int k = ks * 32 + 8 * g + e;
             N.w4[ks][e] = to_bf16(r < kOut ? w[oW4 + r * kH + k] : 0.0f);
         }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int c = 4 * g + i;
-        N.b4[i] = c < kOut ? w[oB4 + c] : 0.0f;
-    }
+    N.w = w;
 }
 
 // Writes the features of one tetrahedron (12 floats) as row t of an input
@@ -201,9 +190,14 @@ __device__ __forceinline__ void xor_cells(float (&p)[kOut], int r)
 // 16-tet tile is read completely before it is written).
 template <int KS, int IN_STRIDE>
 __device__ __forceinline__ void hidden_layer(const __bf16* in, __bf16* out, __bf16* sp,
-                                             const bf16x8 (&w)[4][KS], const f32x4 (&b)[4])
+                                             const bf16x8 (&w)[4][KS], const float* __restrict__ bias)
 {
     const int lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+    f32x4 b[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) b[mt][i] = bias[mt * 16 + 4 * g + i];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
         const int t = nt * 16 + col;
@@ -237,7 +231,9 @@ __device__ __forceinline__ void output_layer(const __bf16* h3, float* lg, const 
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
         const int t = nt * 16 + col;
-        f32x4 acc = N.b4;
+        f32x4 acc;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] = 4 * g + i < kOut ? N.w[oB4 + 4 * g + i] : 0.0f;
         acc = mfma(N.w4[0], ld8(h3 + t * kHS + 8 * g), acc);
         acc = mfma(N.w4[1], ld8(h3 + t * kHS + 32 + 8 * g), acc);
         if (g < 2) *reinterpret_cast<f32x4*>(lg + t * kOut + 4 * g) = acc;
@@ -477,9 +473,9 @@ __global__ __launch_bounds__(64) void forward_kernel(NetIO io)
         }
         put_features(hb + lane * kHS, x);
         __syncthreads();
-        hidden_layer<1, kHS>(hb, hb, nullptr, N.w1, N.b1);
-        hidden_layer<2, kHS>(hb, hb, nullptr, N.w2, N.b2);
-        hidden_layer<2, kHS>(hb, hb, nullptr, N.w3, N.b3);
+        hidden_layer<1, kHS>(hb, hb, nullptr, N.w1, N.w + oB1);
+        hidden_layer<2, kHS>(hb, hb, nullptr, N.w2, N.w + oB2);
+        hidden_layer<2, kHS>(hb, hb, nullptr, N.w3, N.w + oB3);
         output_layer(hb, lg, N);
         __syncthreads();
         if (s < io.n) {
@@ -619,9 +615,9 @@ __global__ __launch_bounds__(64) void backward_kernel(NetIO io)
             put_features(row, x);
         }
         __syncthreads();
-        hidden_layer<1, kXS>(L.x, L.h1, L.s1, N.w1, N.b1);
-        hidden_layer<2, kHS>(L.h1, L.h2, L.s2, N.w2, N.b2);
-        hidden_layer<2, kHS>(L.h2, L.h3, L.s3, N.w3, N.b3);
+        hidden_layer<1, kXS>(L.x, L.h1, L.s1, N.w1, N.w + oB1);
+        hidden_layer<2, kHS>(L.h1, L.h2, L.s2, N.w2, N.w + oB2);
+        hidden_layer<2, kHS>(L.h2, L.h3, L.s3, N.w3, N.w + oB3);
         float* lg = reinterpret_cast<float*>(L.gb);
         output_layer(L.h3, lg, N);
         __syncthreads();
@@ -758,7 +754,7 @@ __global__ void adam_kernel(float* w, const float* g, float* m, float* v, int64_
 constexpr int kRing = 128;  // per-wave queue of eligible tetrahedra
 
 template <typename OutT>
-__global__ __launch_bounds__(64) void surrogate_deposit_kernel(UniformArgs P, int64_t n_chunks)
+__global__ __launch_bounds__(64, 2) void surrogate_deposit_kernel(UniformArgs P, int64_t n_chunks)
 {
     __shared__ __attribute__((aligned(16))) float qx[kRing * kIn];
     __shared__ int qm[kRing * 4];  // mask, lo wrapped into [0, nc) per axis
@@ -786,9 +782,9 @@ __global__ __launch_bounds__(64) void surrogate_deposit_kernel(UniformArgs P, in
             put_features(hb + lane * kHS, x);
         }
         __syncthreads();
-        hidden_layer<1, kHS>(hb, hb, nullptr, N.w1, N.b1);
-        hidden_layer<2, kHS>(hb, hb, nullptr, N.w2, N.b2);
-        hidden_layer<2, kHS>(hb, hb, nullptr, N.w3, N.b3);
+        hidden_layer<1, kHS>(hb, hb, nullptr, N.w1, N.w + oB1);
+        hidden_layer<2, kHS>(hb, hb, nullptr, N.w2, N.w + oB2);
+        hidden_layer<2, kHS>(hb, hb, nullptr, N.w3, N.w + oB3);
         output_layer(hb, lg, N);
         __syncthreads();
         if (lane < n) {

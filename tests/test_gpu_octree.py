@@ -87,6 +87,19 @@ def test_leaf_deposit_matches_oracle(psd, orc, case):
                        atol=1e-12)
 
 
+@pytest.mark.parametrize("tuning", [(1024, 8, 1), (512, 4, 0), (2048, 8, 0)])
+def test_leaf_deposit_launch_shapes_agree(psd, orc, tuning):
+    """Cost order (no skipping of leafless levels) and other LDS buffers give the same
+    leaves; the tree here has leaves at several levels and leafless ones above them."""
+    name, mk, B, L, S, T = next(c for c in CASES if c[0] == "zel32_adaptive")
+    pos = mk()
+    pt = _dev(pos)
+    tree = psd.build_octree(pt, block=B, max_level=L, subblock=S, threshold=T)
+    base = psd.deposit_octree(pt, tree).double().cpu().numpy()
+    got = psd.deposit_octree(pt, tree, tuning=tuning).double().cpu().numpy()
+    assert np.abs(got - base).sum() / np.abs(base).sum() <= 1e-6
+
+
 @functools.lru_cache(maxsize=1)
 def _clump512():
     from synth import workload
