@@ -344,8 +344,8 @@ def main() -> int:
     if args.cpu_cubes is None:
         args.cpu_cubes = {"clump512_octree": 1_000_000}.get(args.workload, 150_000)
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py: the deposit runs on one GPU only (asked for --gpus {args.gpus}); "
+              "sharding across GPUs is not implemented.", file=sys.stderr)
         return 2
 
     import torch

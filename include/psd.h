@@ -105,7 +105,9 @@ psd_status psd_uniform_workspace_size(const psd_particles* p, const int32_t nc[3
  * volumes of T cap {x<=a+1, y<=b+1} per z-cell (two-plane splitting plus the
  * exact distribution along z), cell volumes by 2-D differences, all FP64.
  * PSD_METHOD_CELL: classify each bbox cell and clip the non-trivial ones
- * exactly, cell-local FP32 (FP64 for distances to the tetrahedron's planes).
+ * exactly, cell-local FP32 (FP64 for distances to the tetrahedron's planes);
+ * it numbers a bbox's cells with 32-bit indices, so it returns
+ * PSD_ERR_UNSUPPORTED when (nc0+1)(nc1+1)(nc2+1) >= 2^31.
  *   pos       DEVICE float [np0][np1][np2][3]
  *   p, nc     host; nc[k] >= 1
  *   out       DEVICE float [nc0][nc1][nc2] (double with PSD_PREC_FP64);

@@ -63,6 +63,13 @@ psd::Tuning tuning_from(const psd_options* opt)
     return t;
 }
 
+// The per-cell method numbers the cells of a bbox with 32-bit indices; a
+// bbox spans at most nc_k + 1 cells per axis.
+bool cell_method_fits(const int32_t nc[3])
+{
+    return ((double)nc[0] + 1.0) * ((double)nc[1] + 1.0) * ((double)nc[2] + 1.0) <= 2147483647.0;
+}
+
 bool tuning_ok(const psd_options* opt)
 {
     if (!opt || !opt->tuning) return true;
@@ -133,6 +140,8 @@ psd_status psd_uniform_workspace_size(const psd_particles* p, const int32_t nc[3
     if (!particles_ok(p)) return fail(PSD_ERR_ARG, "bad particle description");
     if (!grid_ok(nc)) return fail(PSD_ERR_ARG, "bad grid size");
     if (opt && (opt->flags & ~kUniformFlags)) return fail(PSD_ERR_UNSUPPORTED, "unknown flags");
+    if (opt && (opt->flags & PSD_METHOD_CELL) && !cell_method_fits(nc))
+        return fail(PSD_ERR_UNSUPPORTED, "PSD_METHOD_CELL needs (nc0+1)(nc1+1)(nc2+1) < 2^31");
     if (!tuning_ok(opt)) return fail(PSD_ERR_ARG, "bad tuning");
     *bytes = uniform_ws_bytes(p, opt);
     return PSD_OK;
@@ -147,6 +156,8 @@ psd_status psd_deposit_uniform(const float* pos, const psd_particles* p, const i
     if (!grid_ok(nc)) return fail(PSD_ERR_ARG, "bad grid size");
     const uint32_t flags = opt ? opt->flags : 0u;
     if (flags & ~kUniformFlags) return fail(PSD_ERR_UNSUPPORTED, "unknown flags");
+    if ((flags & PSD_METHOD_CELL) && !cell_method_fits(nc))
+        return fail(PSD_ERR_UNSUPPORTED, "PSD_METHOD_CELL needs (nc0+1)(nc1+1)(nc2+1) < 2^31");
     if (!tuning_ok(opt)) return fail(PSD_ERR_ARG, "bad tuning");
     if (!ws || ws_bytes < uniform_ws_bytes(p, opt)) return fail(PSD_ERR_WORKSPACE, "workspace too small");
     if (flags & PSD_SURROGATE) {

@@ -343,7 +343,10 @@ __device__ __forceinline__ int setup_tet(const BoxDesc& P, int64_t tid, CTet& S,
         const double n = (double)P.nc[c];
         S.lo[c] = (int)(lof[c] - n * floor(lof[c] / n));
     }
-    int ncell = ok ? e[0] * e[1] * e[2] : 0;
+    // a bbox can exceed 2^31 cells on grids above ~1290 cells per axis: the
+    // count only picks the tiled walk, which handles any size
+    const int64_t ncell64 = ok ? (int64_t)e[0] * e[1] * e[2] : 0;
+    int ncell = ncell64 > 0x7FFFFFFF ? 0x7FFFFFFF : (int)ncell64;
     if (ncell && P.leaf_map && !touches_leaf(P, S.lo, e)) ncell = 0;
     // deposited by the learned surrogate instead
     if (P.skip_small && ncell >= 2 && e[0] <= 2 && e[1] <= 2 && e[2] <= 2) return 0;

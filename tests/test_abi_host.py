@@ -58,6 +58,24 @@ def test_workspace_size_and_argument_errors(psd):
     with pytest.raises(psd.PsdError) as e:
         psd.uniform_workspace_size((8, 8, 8), 16, flags=1 << 20)
     assert e.value.code == psd.PSD_ERR_UNSUPPORTED
+    # the per-cell method numbers bbox cells in 32 bits: refused where a bbox could overflow
+    assert psd.uniform_workspace_size((8, 8, 8), 1289, flags=psd.PSD_METHOD_CELL) > 0
+    with pytest.raises(psd.PsdError) as e:
+        psd.uniform_workspace_size((8, 8, 8), 1290, flags=psd.PSD_METHOD_CELL)
+    assert e.value.code == psd.PSD_ERR_UNSUPPORTED
+    assert psd.uniform_workspace_size((8, 8, 8), 1290) > 0  # the default method has no limit
+    # the surrogate flag needs the default method and parameters
+    with pytest.raises(psd.PsdError):
+        L = psd.lib()
+        p = psd.Particles()
+        for a in range(3):
+            p.np[a] = 4
+        p.box, p.total_mass = 1.0, 1.0
+        nc = (C.c_int32 * 3)(8, 8, 8)
+        o = psd.Options(psd.PSD_SURROGATE, None, None, None)
+        fake = C.c_void_p(0x1000)
+        psd._check(L.psd_deposit_uniform(fake, C.byref(p), nc, fake, None, C.byref(o), fake,
+                                          1 << 30, None), "psd_deposit_uniform")
 
 
 def test_deposit_rejects_bad_arguments_before_launch(psd):
