@@ -322,6 +322,41 @@ def bench_batched(args, torch, psd) -> dict:
     return line
 
 
+def bench_surrogate_workload(args, torch, psd) -> dict:
+    """256^3 -> 64^3 (0.25 cells per spacing, ~72% of tets eligible for the network):
+    the exact path and the surrogate path on the same positions."""
+    from synth import workload
+    dev = torch.device("cuda:0")
+    pos, p = workload("zel256_g64")
+    nc = p["nc"]
+    ntet = 6 * p["np"] ** 3
+    pt = torch.from_numpy(pos).to(dev)
+    if not os.path.exists(SURROGATE_WEIGHTS):
+        raise SystemExit(f"{SURROGATE_WEIGHTS} is missing: train with paper_1612_09491_amd/train.py")
+    w = torch.from_numpy(np.load(SURROGATE_WEIGHTS).astype(np.float32)).to(dev)
+    reps = max(1, args.steps)
+    ms_x, g_x = time_deposit(psd, torch, pt, nc, 0, reps)
+    ms_s, g_s = time_deposit(psd, torch, pt, nc, psd.PSD_SURROGATE, reps, surrogate=w)
+    st = torch.zeros(8, dtype=torch.int64, device=dev)
+    psd.deposit_uniform(pt, nc, flags=psd.PSD_SURROGATE, stats=st, surrogate=w)
+    line = {"value": ntet / (ms_s / 1e3), "ms_per_step": ms_s, "dtype": "bf16+f64",
+            "config": {"workload": "zel256_g64", "particles": p["np"] ** 3, "tets": ntet,
+                       "grid": [nc, nc, nc], "rms_displacement_spacings": p["rms"],
+                       "seed": p["seed"], "weights": os.path.basename(SURROGATE_WEIGHTS),
+                       "path": "learned surrogate (BF16 MFMA) for tets within 2x2x2 cells, "
+                               "exact FP64 for the others"},
+            "eligible_tets": int(st[6].item()),
+            "density_l1_vs_exact": rel_l1(g_s.double(), g_x.double()),
+            "exact": {"tets_per_s": ntet / (ms_x / 1e3), "ms": ms_x}}
+    if not args.no_cpu:
+        o = oracle_sample_counts([pos], args.cpu_cubes, 12345, lambda i: nc)
+        line["cpu_baseline"] = {"value": o["tets"] / o["seconds"], "unit": "tets/s",
+                                "cores": o["threads"], "kind": "oracle",
+                                "sample": f"{o['tets'] // 6} random Lagrangian cubes, exact FP64 "
+                                          f"polytope clipper, {o['seconds']:.1f} s"}
+    return line
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -335,14 +370,15 @@ def main() -> int:
     ap.add_argument("--no-cell", action="store_true",
                     help="skip the per-cell (cell-local FP32) method's timing")
     ap.add_argument("--workload", default=WORKLOAD,
-                    choices=[WORKLOAD, "clump512_octree", "batched64"],
+                    choices=[WORKLOAD, "clump512_octree", "batched64", "zel256_g64"],
                     help="the benchmark workload (default) or a secondary one")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy, whose FETCH_SIZE and "
                          "WRITE_SIZE counters scale the deposit kernel's")
     args = ap.parse_args()
     if args.cpu_cubes is None:
-        args.cpu_cubes = {"clump512_octree": 1_000_000}.get(args.workload, 150_000)
+        args.cpu_cubes = {"clump512_octree": 1_000_000, "zel256_g64": 1_500_000}.get(
+            args.workload, 150_000)
     if args.gpus != 1:
         print(f"bench.py: the deposit runs on one GPU only (asked for --gpus {args.gpus}); "
               "sharding across GPUs is not implemented.", file=sys.stderr)
@@ -356,7 +392,8 @@ def main() -> int:
         raise SystemExit(f"{psd.LIB_PATH} is missing: run __graft_entry__.build() first")
 
     if args.workload != WORKLOAD:
-        fn = {"clump512_octree": bench_octree, "batched64": bench_batched}[args.workload]
+        fn = {"clump512_octree": bench_octree, "batched64": bench_batched,
+              "zel256_g64": bench_surrogate_workload}[args.workload]
         extra = fn(args, torch, psd)
         line = {"metric": METRIC, "unit": "tets/s", "n_gpus": 1, "steps": args.steps,
                 "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",

@@ -94,7 +94,9 @@ typedef struct {
                                  network for PSD_SURROGATE; else ignored     */
 } psd_options;
 
-/* Workspace bytes (host out) needed by psd_deposit_uniform for this problem. */
+/* Workspace bytes (host out) needed by psd_deposit_uniform for this problem
+ * and these options (PSD_SURROGATE adds 8 bytes per 64 tetrahedra; the
+ * cost-ordered tuning adds its chunk order). */
 psd_status psd_uniform_workspace_size(const psd_particles* p, const int32_t nc[3],
                                       const psd_options* opt, size_t* bytes);
 

@@ -82,7 +82,11 @@ size_t uniform_ws_bytes(const psd_particles* p, const psd_options* opt)
 {
     const int64_t ntet = 6 * (int64_t)p->np[0] * p->np[1] * p->np[2];
     const bool ordered = tuning_from(opt).ordered != 0;
-    return psd::queue_workspace_bytes((ntet + 63) / 64, 1, ordered);
+    size_t b = psd::queue_workspace_bytes((ntet + 63) / 64, 1, ordered);
+    // with the surrogate: one 64-bit word per 64-tet chunk marking the tets
+    // the exact path still deposits
+    if (opt && (opt->flags & PSD_SURROGATE)) b = psd::surrogate_mask_offset(b) + psd::surrogate_mask_bytes(ntet);
+    return b;
 }
 
 bool octree_params_ok(const psd_octree_params* op)

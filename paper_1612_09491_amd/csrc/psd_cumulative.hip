@@ -432,7 +432,9 @@ __global__ __launch_bounds__(kWave) void queue_kernel(QueueArgs Q)
         int ncell = 0;
         if (tid < P.ntet) {
             ++n_tet;
-            ncell = setup_tet<OutT>(P, tid, slots[lane], macc, n_pair, n_nz, n_inv, n_deg);
+            // tets already deposited by the surrogate are not built again
+            const bool mine = !P.exact_mask || ((P.exact_mask[g - P.chunk_begin] >> lane) & 1ull);
+            if (mine) ncell = setup_tet<OutT>(P, tid, slots[lane], macc, n_pair, n_nz, n_inv, n_deg);
         }
         slots[lane].ncell = ncell;
         __syncthreads();

@@ -61,6 +61,8 @@ struct BoxDesc {
     int leaf_block;
     int leaf_side;
     int skip_small;            // leave bboxes of 2..8 cells within 2x2x2 to the surrogate
+    // per 64-tet chunk, the tets left to this deposit (bit = lane), or null
+    const unsigned long long* exact_mask;
 };
 
 struct Tuning {
@@ -154,7 +156,13 @@ hipError_t launch_surrogate_backward(const float* w, const float* feat, const do
                                      double* loss, hipStream_t stream);
 hipError_t launch_surrogate_adam(float* w, const float* grad, float* m, float* v, int64_t step,
                                  float lr, float beta1, float beta2, float eps, hipStream_t stream);
-// Deposits the tetrahedra the exact path leaves to the surrogate (P.surrogate set).
-hipError_t launch_surrogate_deposit(const UniformArgs& P, bool fp64, hipStream_t stream);
+// Deposits the tetrahedra the exact path leaves to the surrogate (P.surrogate
+// set) and, when exact_mask is not null, marks per 64-tet chunk the ones the
+// exact path still has to deposit.
+hipError_t launch_surrogate_deposit(const UniformArgs& P, bool fp64, unsigned long long* exact_mask,
+                                    hipStream_t stream);
+// Workspace placement of that mask after `base` bytes, and its size.
+inline size_t surrogate_mask_offset(size_t base) { return (base + 255) & ~(size_t)255; }
+inline size_t surrogate_mask_bytes(int64_t ntet) { return (size_t)((ntet + 63) / 64) * 8; }
 
 }  // namespace psd

@@ -754,7 +754,8 @@ __global__ void adam_kernel(float* w, const float* g, float* m, float* v, int64_
 constexpr int kRing = 128;  // per-wave queue of eligible tetrahedra
 
 template <typename OutT>
-__global__ __launch_bounds__(64, 2) void surrogate_deposit_kernel(UniformArgs P, int64_t n_chunks)
+__global__ __launch_bounds__(64, 2) void surrogate_deposit_kernel(UniformArgs P, int64_t n_chunks,
+                                                                   unsigned long long* exact_mask)
 {
     __shared__ __attribute__((aligned(16))) float qx[kRing * kIn];
     __shared__ int qm[kRing * 4];  // mask, lo wrapped into [0, nc) per axis
@@ -766,7 +767,7 @@ __global__ __launch_bounds__(64, 2) void surrogate_deposit_kernel(UniformArgs P,
     const int lane = threadIdx.x;
     int head = 0, qn = 0;
     double macc = 0.0;
-    unsigned long long n_sur = 0, n_nz = 0;
+    unsigned long long n_sur = 0, n_nz = 0, n_inv = 0;
 
     auto run = [&](int n) {
         if (lane < n) {
@@ -836,8 +837,14 @@ __global__ __launch_bounds__(64, 2) void surrogate_deposit_kernel(UniformArgs P,
             Tet64 T;
             make_tet(P.pos, P.np[0], P.np[1], P.np[2], P.scale, P.nc, ii, jj, kk, p, T);
             e = small_tet(T, 2, vr, lo, span);
+            // the exact pass skips these tets, so their orientation is counted here
+            if (e && (double)kuhn_sign(p) * T.D < 0.0) ++n_inv;
         }
         const uint64_t bal = __ballot(e);
+        if (exact_mask) {
+            const uint64_t rest = __ballot(tid < P.ntet && !e);
+            if (lane == 0) exact_mask[chunk] = rest;
+        }
         if (e) {
             const int rank = (int)__popcll(bal & ((1ull << lane) - 1ull));
             const int slot = (head + qn + rank) & (kRing - 1);
@@ -867,15 +874,17 @@ __global__ __launch_bounds__(64, 2) void surrogate_deposit_kernel(UniformArgs P,
     macc = wave_sum(macc);
     if (lane == 0 && P.mass_sum && macc != 0.0) atomicAdd(P.mass_sum, macc);
     if (P.stats) {
-        unsigned long long a = n_sur, b = n_nz;
+        unsigned long long a = n_sur, b = n_nz, c = n_inv;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
             a += __shfl_xor(a, off, 64);
             b += __shfl_xor(b, off, 64);
+            c += __shfl_xor(c, off, 64);
         }
         if (lane == 0) {
             if (a) atomicAdd(P.stats + 6, a);
             if (b) atomicAdd(P.stats + 3, b);
+            if (c) atomicAdd(P.stats + 4, c);
         }
     }
 }
@@ -990,15 +999,18 @@ hipError_t launch_surrogate_adam(float* w, const float* grad, float* m, float* v
     return hipGetLastError();
 }
 
-hipError_t launch_surrogate_deposit(const UniformArgs& P, bool fp64, hipStream_t stream)
+hipError_t launch_surrogate_deposit(const UniformArgs& P, bool fp64, unsigned long long* exact_mask,
+                                    hipStream_t stream)
 {
     const int64_t n_chunks = (P.ntet + 63) / 64;
     if (n_chunks == 0) return hipSuccess;
     int grid = net_grid(P.ntet);
     if (fp64)
-        hipLaunchKernelGGL(surrogate_deposit_kernel<double>, dim3(grid), dim3(64), 0, stream, P, n_chunks);
+        hipLaunchKernelGGL(surrogate_deposit_kernel<double>, dim3(grid), dim3(64), 0, stream, P, n_chunks,
+                           exact_mask);
     else
-        hipLaunchKernelGGL(surrogate_deposit_kernel<float>, dim3(grid), dim3(64), 0, stream, P, n_chunks);
+        hipLaunchKernelGGL(surrogate_deposit_kernel<float>, dim3(grid), dim3(64), 0, stream, P, n_chunks,
+                           exact_mask);
     return hipGetLastError();
 }
 

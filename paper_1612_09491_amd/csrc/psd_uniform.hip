@@ -469,10 +469,21 @@ hipError_t launch_deposit_uniform(const UniformArgs& P, bool fp64, bool accumula
                                (int64_t)1, 0.0);
     }
     if (!cell_method) {
-        const BoxDesc b = box_from_uniform(P);
-        hipError_t e = launch_queue(&b, 1, fp64, tune, ws, ws_bytes, P.stats, stream);
-        if (e != hipSuccess || !P.surrogate) return e;
-        return launch_surrogate_deposit(P, fp64, stream);
+        BoxDesc b = box_from_uniform(P);
+        size_t qbytes = ws_bytes;
+        if (P.surrogate) {
+            // the network's pass first: it marks the tets left to the exact pass
+            const int64_t n_chunks = (P.ntet + kWave - 1) / kWave;
+            qbytes = queue_workspace_bytes(n_chunks, 1, tune.ordered != 0);
+            const size_t off = surrogate_mask_offset(qbytes);
+            if (off + surrogate_mask_bytes(P.ntet) > ws_bytes) return hipErrorInvalidValue;
+            unsigned long long* mask =
+                reinterpret_cast<unsigned long long*>(static_cast<char*>(ws) + off);
+            hipError_t e = launch_surrogate_deposit(P, fp64, mask, stream);
+            if (e != hipSuccess) return e;
+            b.exact_mask = mask;
+        }
+        return launch_queue(&b, 1, fp64, tune, ws, qbytes, P.stats, stream);
     }
     if (P.surrogate) return hipErrorInvalidValue;
     const int64_t nchunk = (P.ntet + kWave - 1) / kWave;

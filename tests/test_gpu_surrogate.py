@@ -185,6 +185,7 @@ def test_surrogate_deposit_matches_composition(psd, orc, fp64):
                               surrogate=_dev(w)).double().cpu().numpy()
     st = st.cpu().numpy()
     assert st[6] == n_el and st[0] == cnt["n_tet"]
+    assert st[4] == cnt["n_inverted"] and st[5] == cnt["n_degenerate"]
     assert abs(float(ms.item()) - 1.0) <= 1e-12
     assert abs(got.sum() - 1.0) <= (1e-12 if fp64 else 1e-5)
     # the network's share of the grid is held to the network tolerance
