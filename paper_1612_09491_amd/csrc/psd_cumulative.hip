@@ -174,7 +174,19 @@ __device__ __forceinline__ double zdist_below(const ZDist& Z, double k)
     return k <= Z.s0 ? 0.0 : F;
 }
 
-// Adds frac * (share of each z-cell of the tile) for one piece.
+// LDS add with no returned value (one ds_add_f64): the lane does not wait for
+// the old value, as a read-modify-write of its own column would.
+__device__ __forceinline__ void lds_add(double* p, double v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Adds frac * (share of each z-cell of the tile) for one piece.  The levels
+// are walked region by region of the piecewise cubic, so each step evaluates
+// one cubic only; every cubic is scaled by frac up front.  On (s1, s2) the
+// cubic is expanded in t = k - s1: each expanded term is bounded by 1 there
+// (t <= s2 - s1 <= s3 - s1 and s1 - s0 <= s2 - s0, s3 - s0), so Horner's
+// rule loses only a few ulps.
 __device__ __forceinline__ void spread_z(const double z[4], double frac, const Tile& t,
                                          double* Dcol)
 {
@@ -184,11 +196,39 @@ __device__ __forceinline__ void spread_z(const double z[4], double frac, const T
     const int lA = max(lfirst, t.l0);
     const int lB = min((int)floor(Z.s3), t.l0 + t.tl - 1);
     if (lA > lB) return;
-    double Fprev = (lA <= lfirst) ? 0.0 : zdist_below(Z, (double)lA);
-    for (int l = lA; l <= lB; ++l) {
-        const double Fnext = zdist_below(Z, (double)(l + 1));
-        Dcol[l - t.l0] += frac * (Fnext - Fprev);
-        Fprev = Fnext;
+    double Fprev = (lA <= lfirst) ? 0.0 : frac * zdist_below(Z, (double)lA);
+    double* p = Dcol + (lA - t.l0);
+    double k = (double)(lA + 1);       // upper plane of the level
+    const double kB = (double)(lB + 1);
+    // k <= s1
+    const double fA = frac * Z.iA;
+    const double kLow = fmin(Z.s1, kB);
+    for (; k <= kLow; k += 1.0, ++p) {
+        const double u = k - Z.s0;
+        const double F = fA * (u * u * u);
+        lds_add(p, F - Fprev);
+        Fprev = F;
+    }
+    // s1 < k < s2
+    const double a = Z.s1 - Z.s0;
+    const double A = Z.r20 * Z.r30, B = Z.r20 * Z.r31;
+    const double c0 = frac * (A * a * a);
+    const double c1 = frac * (a * (A * (2.0 - Z.r31 * a) + B));
+    const double c2 = frac * (A * (1.0 - 2.0 * a * Z.r31) + B * (1.0 - a * Z.r21) + Z.r21 * Z.r31);
+    const double c3 = -frac * (A * Z.r31 + B * Z.r21);
+    for (; k < Z.s2 && k <= kB; k += 1.0, ++p) {
+        const double tt = k - Z.s1;
+        const double F = fma(fma(fma(c3, tt, c2), tt, c1), tt, c0);
+        lds_add(p, F - Fprev);
+        Fprev = F;
+    }
+    // s2 <= k; the last level's upper plane lies above s3
+    const double fC = frac * Z.iC;
+    for (; k <= kB; k += 1.0, ++p) {
+        const double w = Z.s3 - k;
+        const double F = w > 0.0 ? frac - fC * (w * w * w) : frac;
+        lds_add(p, F - Fprev);
+        Fprev = F;
     }
 }
 
