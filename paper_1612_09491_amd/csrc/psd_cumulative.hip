@@ -19,9 +19,10 @@
 // over a table of independent boxes -- one periodic grid, the levels of an
 // octree, or a batch of uneven boxes.  Per chunk, lanes build 64 tetrahedra
 // into LDS; small ones are batched so that their D arrays share an LDS
-// buffer, larger ones are tiled.  Phase 1 spreads (tet, column) pairs over
-// lanes, phase 2 spreads (tet, cell) pairs and scatters the non-zero cell
-// masses with global atomics.
+// buffer, larger ones are tiled.  (tet, column) pairs go over the lanes 64
+// at a time: phase 1 fills a window's D columns, phase 2 then walks the
+// cells of the same columns, takes the differences and scatters the
+// non-zero cell masses with global atomics.
 #include <string.h>
 
 #include <vector>
@@ -528,7 +529,11 @@ __global__ __launch_bounds__(kWave) void queue_kernel(QueueArgs Q)
             __syncthreads();
             if (nt == 0) continue;
 
-            // Phase 1: (tile, column) pairs over lanes.
+            // (tile, column) pairs over lanes, 64 at a time.  Phase 1 fills
+            // the window's D columns; columns are numbered row by row, so the
+            // lower neighbours (a-1, b), (a, b-1), (a-1, b-1) of every column
+            // are in this window or an earlier one, and right after a barrier
+            // phase 2 can walk the cells of the window's own columns.
             {
                 const int64_t c = lane < nt ? tile_cols(tiles[lane]) : 0;
                 int64_t incl = c;
@@ -542,8 +547,9 @@ __global__ __launch_bounds__(kWave) void queue_kernel(QueueArgs Q)
                 const int64_t total = __shfl(incl, kWave - 1, kWave);
                 for (int64_t base = 0; base < total; base += kWave) {
                     const int64_t idx = base + lane;
+                    int lo = 0, r = 0;
                     if (idx < total) {
-                        int lo = 0, hi = nt - 1;
+                        int hi = nt - 1;
                         while (lo < hi) {
                             const int mid = (lo + hi) >> 1;
                             if (s_incl[mid] > idx) hi = mid;
@@ -551,7 +557,7 @@ __global__ __launch_bounds__(kWave) void queue_kernel(QueueArgs Q)
                         }
                         const Tile t = tiles[lo];
                         const CTet& S = slots[t_slot[lo]];
-                        const int r = (int)(idx - (s_incl[lo] - tile_cols(t)));
+                        r = (int)(idx - (s_incl[lo] - tile_cols(t)));
                         const int wb = t.tb + t.hb;
                         const int qa = fdivi(r, t.inv_wb);
                         const int a = t.a0 - t.ha + qa;
@@ -559,65 +565,48 @@ __global__ __launch_bounds__(kWave) void queue_kernel(QueueArgs Q)
                         column(S, a, b, t, Dbuf + t.doff + r * t.tl);
                         ++n_col;
                     }
-                }
-                __syncthreads();
-            }
-            // Phase 2: (tile, cell) pairs over lanes.
-            {
-                const int64_t c = lane < nt ? tile_cells(tiles[lane]) : 0;
-                int64_t incl = c;
-#pragma unroll
-                for (int off = 1; off < kWave; off <<= 1) {
-                    const int64_t y = __shfl_up(incl, off, kWave);
-                    if (lane >= off) incl += y;
-                }
-                s_incl[lane] = incl;
-                __syncthreads();
-                const int64_t total = __shfl(incl, kWave - 1, kWave);
-                for (int64_t base = 0; base < total; base += kWave) {
-                    const int64_t idx = base + lane;
+                    __syncthreads();
+                    // Phase 2: the cells (i, j, l) of this lane's column, l
+                    // walking the tile's levels; halo columns have no cells.
                     if (idx < total) {
-                        int lo = 0, hi = nt - 1;
-                        while (lo < hi) {
-                            const int mid = (lo + hi) >> 1;
-                            if (s_incl[mid] > idx) hi = mid;
-                            else lo = mid + 1;
-                        }
                         const Tile t = tiles[lo];
                         const CTet& S = slots[t_slot[lo]];
-                        const int r = (int)(idx - (s_incl[lo] - tile_cells(t)));
-                        // r -> (i, j, l) within the tile, l fastest
-                        const int ij = fdivi(r, t.inv_tl);
-                        const int l = r - ij * t.tl;
-                        const int i = fdivi(ij, t.inv_tb);
-                        const int j = ij - i * t.tb;
                         const int wb = t.tb + t.hb;
-                        const double* D = Dbuf + t.doff;
-                        const int ca = i + t.ha, cb = j + t.hb;
-                        const double d11 = D[(ca * wb + cb) * t.tl + l];
-                        const bool has_a = (t.a0 + i) > 0, has_b = (t.b0 + j) > 0;
-                        const double d01 = has_a ? D[((ca - 1) * wb + cb) * t.tl + l] : 0.0;
-                        const double d10 = has_b ? D[(ca * wb + cb - 1) * t.tl + l] : 0.0;
-                        const double d00 = (has_a && has_b) ? D[((ca - 1) * wb + cb - 1) * t.tl + l] : 0.0;
-                        const double V = (d11 - d01) - (d10 - d00);
-                        ++n_pair;
-                        // differences of values up to 1 carry ~1e-16 noise: drop it
-                        if (V > 4e-15) {
-                            // walk-frame offsets back to grid axes
-                            const int o0 = t.a0 + i, o1 = t.b0 + j, o2 = t.l0 + l;
-                            const int k0 = walk_axis(S, 0), k1 = walk_axis(S, 1);
-                            const int ox = k0 == 0 ? o0 : (k1 == 0 ? o1 : o2);
-                            const int oy = k0 == 1 ? o0 : (k1 == 1 ? o1 : o2);
-                            const int oz = k0 == 2 ? o0 : (k1 == 2 ? o1 : o2);
-                            const int gx = wrap_add(S.lo[0], ox, P.nc[0]);
-                            const int gy = wrap_add(S.lo[1], oy, P.nc[1]);
-                            const int gz = wrap_add(S.lo[2], oz, P.nc[2]);
-                            const int64_t gi = out_index(P, gx, gy, gz);
-                            if (gi >= 0) {
-                                ++n_nz;
-                                const double mass = P.m * V;
-                                atomicAdd(out + gi, (OutT)(mass * P.out_scale));
-                                macc += mass;
+                        const int ca = fdivi(r, t.inv_wb), cb = r - ca * wb;
+                        const int i = ca - t.ha, j = cb - t.hb;
+                        if (i >= 0 && j >= 0) {
+                            const bool has_a = (t.a0 + i) > 0, has_b = (t.b0 + j) > 0;
+                            const double* D11 = Dbuf + t.doff + r * t.tl;
+                            const double* D01 = D11 - wb * t.tl;
+                            const double* D10 = D11 - t.tl;
+                            const double* D00 = D01 - t.tl;
+                            // grid cell of level 0, and the grid axis the levels walk
+                            const int o0 = t.a0 + i, o1 = t.b0 + j, o2 = t.l0;
+                            const int k0 = walk_axis(S, 0), k1 = walk_axis(S, 1), k2 = walk_axis(S, 2);
+                            const int gx = wrap_add(S.lo[0], k0 == 0 ? o0 : (k1 == 0 ? o1 : o2), P.nc[0]);
+                            const int gy = wrap_add(S.lo[1], k0 == 1 ? o0 : (k1 == 1 ? o1 : o2), P.nc[1]);
+                            const int gz = wrap_add(S.lo[2], k0 == 2 ? o0 : (k1 == 2 ? o1 : o2), P.nc[2]);
+                            const int gw = k2 == 0 ? gx : (k2 == 1 ? gy : gz);
+                            const int nw = k2 == 0 ? P.nc[0] : (k2 == 1 ? P.nc[1] : P.nc[2]);
+                            n_pair += t.tl;
+                            for (int l = 0; l < t.tl; ++l) {
+                                const double d11 = D11[l];
+                                const double d01 = has_a ? D01[l] : 0.0;
+                                const double d10 = has_b ? D10[l] : 0.0;
+                                const double d00 = (has_a && has_b) ? D00[l] : 0.0;
+                                const double V = (d11 - d01) - (d10 - d00);
+                                // differences of values up to 1 carry ~1e-16 noise: drop it
+                                if (V > 4e-15) {
+                                    const int w = wrap_add(gw, l, nw);
+                                    const int64_t gi = out_index(P, k2 == 0 ? w : gx, k2 == 1 ? w : gy,
+                                                                 k2 == 2 ? w : gz);
+                                    if (gi >= 0) {
+                                        ++n_nz;
+                                        const double mass = P.m * V;
+                                        atomicAdd(out + gi, (OutT)(mass * P.out_scale));
+                                        macc += mass;
+                                    }
+                                }
                             }
                         }
                     }
