@@ -262,7 +262,7 @@ def bench_octree(args, torch, psd) -> dict:
         line["roofline"] = {"bound": "alu", "achieved": achieved / 1e12,
                             "peak": PEAK_VALU_OPS / 1e12, "unit": "Top/s",
                             "frac": achieved / PEAK_VALU_OPS, "traffic": None,
-                            "kernel": "queue_kernel<float, 1024>", "kernel_ms": kernel_ms,
+                            "kernel": "queue_kernel<float, 960>", "kernel_ms": kernel_ms,
                             "algorithmic_ops_per_tet": o["ops_per_tet"]}
     return line
 
@@ -484,7 +484,7 @@ def main() -> int:
             "unit": "Top/s",
             "frac": achieved / PEAK_VALU_OPS,
             "traffic": traffic["bytes_per_launch"] if traffic else None,
-            "kernel": "queue_kernel<float, 1024>",
+            "kernel": "queue_kernel<float, 960>",
             "kernel_ms": kernel_ms,
             "algorithmic_ops_per_tet": ops_per_tet,
         }

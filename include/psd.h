@@ -73,8 +73,9 @@ typedef struct {
 /* Launch shape of the cumulative deposit (all zero = defaults). */
 typedef struct {
     int32_t lds_cap;      /* FP64 entries of the per-wavefront LDS buffer:
-                             512, 1024 or 2048 (0 = 1024)                     */
-    int32_t waves_per_cu; /* persistent wavefronts per compute unit (0 = 8)   */
+                             512, 960 or 2048 (0 = 960)                       */
+    int32_t waves_per_cu; /* persistent wavefronts per compute unit (0 = as
+                             many as fit: 11 at 960 entries on gfx950)        */
     int32_t ordered;      /* 1: process 64-tet chunks in decreasing estimated
                              cost (bbox cells); 0: in index order             */
     int32_t reserved;     /* must be 0                                        */
@@ -157,9 +158,9 @@ psd_status psd_deposit_batched(const psd_box* boxes, int32_t n_boxes, double* ma
 
 /*
  * Chooses the launch shape (psd_tuning) of psd_deposit_batched for this batch
- * by timing candidates with HIP events on `stream`: LDS buffer of 1024 or
- * 2048 FP64 entries, 4 or 8 wavefronts per compute unit, chunks in index or
- * cost order.  The boxes' outputs are overwritten with a valid deposit.  If
+ * by timing candidates with HIP events on `stream`: LDS buffer of 960 or
+ * 2048 FP64 entries, all the wavefronts that fit a compute unit or half of
+ * them, chunks in index or cost order.  The boxes' outputs are overwritten with a valid deposit.  If
  * cache_path (host string, may be NULL) names a JSON file, a result for the
  * same device and batch signature is read from it instead of measuring, and
  * new results are added to it.  The workspace must be sized for ordered

@@ -117,7 +117,7 @@ static bool cache_lookup(const char* path, const std::string& key, Tuning& t, do
     c = (int)dc;
     w = (int)dw;
     o = (int)dord;
-    if (!(c == 512 || c == 1024 || c == 2048) || w < 1 || w > 64) return false;
+    if (!(c == 512 || c == 960 || c == 2048) || w < 1 || w > 64) return false;
     t.cap = c;
     t.waves_per_cu = w;
     t.ordered = o ? 1 : 0;
@@ -185,8 +185,7 @@ hipError_t autotune_batched(const psd_box* boxes, int n, uint32_t flags, void* w
         if (cache_lookup(cache_path, key, best, best_ms)) return hipSuccess;
     }
     const bool density = (flags & PSD_OUT_DENSITY) != 0;
-    const int caps[2] = {1024, 2048};
-    const int waves[2] = {4, 8};
+    const int caps[2] = {960, 2048};
     hipEvent_t e0, e1;
     hipError_t e = hipEventCreate(&e0);
     if (e != hipSuccess) return e;
@@ -204,7 +203,10 @@ hipError_t autotune_batched(const psd_box* boxes, int n, uint32_t flags, void* w
             for (int wi = 0; wi < 2 && e == hipSuccess; ++wi) {
                 Tuning t;
                 t.cap = caps[ci];
-                t.waves_per_cu = waves[wi];
+                int fit = 1;
+                e = queue_resident_waves(t.cap, false, fit);
+                if (e != hipSuccess) break;
+                t.waves_per_cu = wi == 0 ? fit : (fit + 1) / 2;
                 t.ordered = ord;
                 e = hipEventRecord(e0, stream);
                 if (e != hipSuccess) break;

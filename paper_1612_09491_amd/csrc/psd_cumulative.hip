@@ -25,6 +25,7 @@
 // non-zero cell masses with global atomics.
 #include <string.h>
 
+#include <atomic>
 #include <vector>
 
 #include "psd_internal.h"
@@ -427,14 +428,21 @@ __device__ __forceinline__ void flush_mass(const BoxDesc& P, double& macc)
     macc = 0.0;
 }
 
+// A 64-tet chunk is built and walked in two halves of 32, which keeps the
+// LDS per wavefront near 13.7 KB at the default buffer (960 entries), so
+// that 11 wavefronts fit a compute unit; the launch bounds hold the
+// registers to three wavefronts per SIMD (two for the 2048-entry buffer,
+// whose LDS allows no more).
+constexpr int kHalf = kWave / 2;
+
 template <typename OutT, int CAP>
-__global__ __launch_bounds__(kWave) void queue_kernel(QueueArgs Q)
+__global__ __launch_bounds__(kWave, (CAP <= 960 ? 3 : 2)) void queue_kernel(QueueArgs Q)
 {
-    __shared__ CTet slots[kWave];
+    __shared__ CTet slots[kHalf];
     __shared__ double Dbuf[CAP];
-    __shared__ Tile tiles[kWave];
-    __shared__ int t_slot[kWave];
-    __shared__ int64_t s_incl[kWave];
+    __shared__ Tile tiles[kHalf];
+    __shared__ int t_slot[kHalf];
+    __shared__ int64_t s_incl[kHalf];
     __shared__ int64_t s_item;
 
     const int lane = threadIdx.x;
@@ -469,24 +477,26 @@ __global__ __launch_bounds__(kWave) void queue_kernel(QueueArgs Q)
         }
         OutT* out = reinterpret_cast<OutT*>(P.out);
 
-        const int64_t tid = (g - P.chunk_begin) * kWave + lane;
+        for (int half = 0; half < 2; ++half) {
+        const int q = half * kHalf + lane;  // tet of the chunk
+        const int64_t tid = (g - P.chunk_begin) * kWave + q;
         int ncell = 0;
-        if (tid < P.ntet) {
+        if (lane < kHalf && tid < P.ntet) {
             ++n_tet;
             // tets already deposited by the surrogate are not built again
-            const bool mine = !P.exact_mask || ((P.exact_mask[g - P.chunk_begin] >> lane) & 1ull);
+            const bool mine = !P.exact_mask || ((P.exact_mask[g - P.chunk_begin] >> q) & 1ull);
             if (mine) ncell = setup_tet<OutT>(P, tid, slots[lane], macc, n_pair, n_nz, n_inv, n_deg);
         }
-        slots[lane].ncell = ncell;
+        if (lane < kHalf) slots[lane].ncell = ncell;
         __syncthreads();
 
-        // Walk the chunk's tetrahedra in tile batches that fit the D buffer.
+        // Walk the half's tetrahedra in tile batches that fit the D buffer.
         int cur = 0;       // next slot to start
         int cur_tile = 0;  // for a tiled tetrahedron, linear index of its next tile
-        while (cur < kWave) {
+        while (cur < kHalf) {
             // Wave-uniform planning (every lane computes the same list).
             int nt = 0, used = 0;
-            while (cur < kWave && nt < kWave) {
+            while (cur < kHalf && nt < kHalf) {
                 const CTet& S = slots[cur];
                 if (S.ncell == 0) {
                     ++cur;
@@ -542,7 +552,7 @@ __global__ __launch_bounds__(kWave) void queue_kernel(QueueArgs Q)
                     const int64_t y = __shfl_up(incl, off, kWave);
                     if (lane >= off) incl += y;
                 }
-                s_incl[lane] = incl;
+                if (lane < kHalf) s_incl[lane] = incl;  // nt <= kHalf
                 __syncthreads();
                 const int64_t total = __shfl(incl, kWave - 1, kWave);
                 for (int64_t base = 0; base < total; base += kWave) {
@@ -615,6 +625,7 @@ __global__ __launch_bounds__(kWave) void queue_kernel(QueueArgs Q)
             }
         }
         __syncthreads();
+        }
     }
     if (cur_box >= 0) flush_mass(P, macc);
 
@@ -738,12 +749,20 @@ QueueLayout queue_layout(int64_t n_chunks, int n_boxes, bool ordered)
 }
 
 template <typename OutT>
+const void* queue_kernel_for(int cap)
+{
+    if (cap <= 512) return reinterpret_cast<const void*>(&queue_kernel<OutT, 512>);
+    if (cap <= 960) return reinterpret_cast<const void*>(&queue_kernel<OutT, 960>);
+    return reinterpret_cast<const void*>(&queue_kernel<OutT, 2048>);
+}
+
+template <typename OutT>
 hipError_t launch_queue_kernel(const QueueArgs& Q, int cap, int grid, hipStream_t stream)
 {
     if (cap <= 512)
         hipLaunchKernelGGL((queue_kernel<OutT, 512>), dim3(grid), dim3(kWave), 0, stream, Q);
-    else if (cap <= 1024)
-        hipLaunchKernelGGL((queue_kernel<OutT, 1024>), dim3(grid), dim3(kWave), 0, stream, Q);
+    else if (cap <= 960)
+        hipLaunchKernelGGL((queue_kernel<OutT, 960>), dim3(grid), dim3(kWave), 0, stream, Q);
     else
         hipLaunchKernelGGL((queue_kernel<OutT, 2048>), dim3(grid), dim3(kWave), 0, stream, Q);
     return hipGetLastError();
@@ -754,10 +773,28 @@ hipError_t launch_queue_kernel(const QueueArgs& Q, int cap, int grid, hipStream_
 Tuning default_tuning()
 {
     Tuning t;
-    t.cap = 1024;
-    t.waves_per_cu = 8;
+    t.cap = 960;
+    t.waves_per_cu = 0;  // as many as fit a compute unit
     t.ordered = 0;
     return t;
+}
+
+hipError_t queue_resident_waves(int cap, bool out_fp64, int& waves)
+{
+    // one kernel instance per (buffer size, output type); the answer only
+    // depends on the instance, so it is asked once
+    static std::atomic<int> known[3][2];
+    const int ci = cap <= 512 ? 0 : (cap <= 960 ? 1 : 2), ti = out_fp64 ? 1 : 0;
+    int n = known[ci][ti].load(std::memory_order_relaxed);
+    if (n == 0) {
+        const void* k = out_fp64 ? queue_kernel_for<double>(cap) : queue_kernel_for<float>(cap);
+        const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, kWave, 0);
+        if (e != hipSuccess) return e;
+        if (n < 1) n = 1;
+        known[ci][ti].store(n, std::memory_order_relaxed);
+    }
+    waves = n;
+    return hipSuccess;
 }
 
 size_t queue_workspace_bytes(int64_t n_chunks, int n_boxes, bool ordered)
@@ -822,7 +859,12 @@ hipError_t launch_queue(const BoxDesc* boxes_in, int n_boxes, bool out_fp64, con
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         cus < 1)
         cus = 256;
-    int64_t grid = (int64_t)cus * (tune.waves_per_cu > 0 ? tune.waves_per_cu : 8);
+    int waves = tune.waves_per_cu;
+    if (waves <= 0) {
+        const hipError_t e = queue_resident_waves(tune.cap, out_fp64, waves);
+        if (e != hipSuccess) return e;
+    }
+    int64_t grid = (int64_t)cus * waves;
     if (grid > n_chunks) grid = n_chunks;
     if (grid < 1) grid = 1;
     return out_fp64 ? launch_queue_kernel<double>(Q, tune.cap, (int)grid, stream)

@@ -66,8 +66,8 @@ struct BoxDesc {
 };
 
 struct Tuning {
-    int cap;            // FP64 entries of the per-wave LDS buffer: 512, 1024 or 2048
-    int waves_per_cu;   // persistent workgroups per compute unit
+    int cap;            // FP64 entries of the per-wave LDS buffer: 512, 960 or 2048
+    int waves_per_cu;   // persistent workgroups per compute unit (0: as many as fit)
     int ordered;        // 1: chunks in decreasing estimated cost
 };
 
@@ -91,6 +91,8 @@ BoxDesc box_from_uniform(const UniformArgs& P);
 hipError_t launch_queue(const BoxDesc* boxes, int n_boxes, bool out_fp64, const Tuning& tune,
                         void* ws, size_t ws_bytes, unsigned long long* stats, hipStream_t stream);
 Tuning default_tuning();
+// Wavefronts of the deposit kernel with this buffer that fit one compute unit.
+hipError_t queue_resident_waves(int cap, bool out_fp64, int& waves);
 
 // ---------------------------------------------------------------------------
 // Octree (Section 4)
