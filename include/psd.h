@@ -287,6 +287,20 @@ psd_status psd_surrogate_examples(const float* pos, const psd_particles* p, cons
                                   int64_t capacity, int64_t* n_out, void* ws, size_t ws_bytes,
                                   void* stream);
 
+/*
+ * Exact labels for given tetrahedra (Section 6.3 splitting, FP64): for each
+ * tetrahedron i, tets[i][4][3] (DEVICE float) are its vertices relative to
+ * the low corner of a 2x2x2 block of cells, in cell units, every coordinate
+ * in [0, 2); frac[i][c] (DEVICE double [n][8], overwritten) = |T cap C_c|/|T|
+ * for cell c = 4 dx + 2 dy + dz of the block.  A zero-volume tetrahedron
+ * (|det| <= 1e-12 (longest edge)^3, the rule of the deposits) gives 1 in its
+ * centroid's cell.  A tetrahedron with a vertex outside [0, 2)^3 or not
+ * finite gives NaN in all 8 entries (no error is returned: the data stay on
+ * the device).  Asynchronous.  Errors: PSD_ERR_ARG (n < 0, null pointers),
+ * PSD_ERR_HIP.
+ */
+psd_status psd_exact_fractions(const float* tets, double* frac, int64_t n, void* stream);
+
 /* probs[n][8] (DEVICE float) = p of the network `params` for feat[n][12] and
  * mask[n].  Asynchronous. */
 psd_status psd_surrogate_forward(const float* params, const float* feat, const uint8_t* mask,

@@ -427,6 +427,8 @@ def _bind_surrogate(L):
                                          C.c_void_p, C.c_void_p, C.c_int64,
                                          C.POINTER(C.c_int64), C.c_void_p, C.c_size_t,
                                          C.c_void_p]
+    L.psd_exact_fractions.restype = C.c_int
+    L.psd_exact_fractions.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
     L.psd_surrogate_forward.restype = C.c_int
     L.psd_surrogate_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                         C.c_void_p, C.c_void_p]
@@ -489,6 +491,23 @@ def surrogate_examples(pos: torch.Tensor, nc, box: float = 1.0, first_cube: int 
     if ids is not None:
         out["tet"] = ids[:n]
     return out
+
+
+def exact_fractions(tets: torch.Tensor, frac: torch.Tensor | None = None,
+                    stream=None) -> torch.Tensor:
+    """Exact overlap fractions [n, 8] (float64) of tetrahedra [n, 4, 3] (float32 vertices
+    relative to the low corner of a 2x2x2 cell block, in [0, 2)) with the block's cells,
+    cell c = 4 dx + 2 dy + dz; NaN rows for vertices outside the block."""
+    L = lib()
+    _bind_surrogate(L)
+    _cuda(tets, torch.float32, (4, 3), "tets")
+    n = int(tets.shape[0])
+    if frac is None:
+        frac = torch.empty((n, 8), dtype=torch.float64, device=tets.device)
+    _cuda(frac, torch.float64, (8,), "frac")
+    _check(L.psd_exact_fractions(tets.data_ptr(), frac.data_ptr(), n, _stream_handle(stream)),
+           "psd_exact_fractions")
+    return frac
 
 
 def surrogate_forward(params: torch.Tensor, feat: torch.Tensor, mask: torch.Tensor,

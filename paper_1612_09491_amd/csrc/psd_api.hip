@@ -372,6 +372,15 @@ psd_status psd_surrogate_examples(const float* pos, const psd_particles* p, cons
     return PSD_OK;
 }
 
+psd_status psd_exact_fractions(const float* tets, double* frac, int64_t n, void* stream)
+{
+    if (n < 0 || n > ((int64_t)1 << 40)) return fail(PSD_ERR_ARG, "bad tetrahedron count");
+    if (n > 0 && (!tets || !frac)) return fail(PSD_ERR_ARG, "null pointer");
+    hipError_t e = psd::launch_exact_fractions(tets, frac, n, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail_hip(e, "exact_fractions");
+    return PSD_OK;
+}
+
 psd_status psd_surrogate_forward(const float* params, const float* feat, const uint8_t* mask,
                                  int64_t n, float* probs, void* stream)
 {

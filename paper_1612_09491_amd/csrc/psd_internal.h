@@ -151,6 +151,7 @@ size_t example_workspace_bytes(int64_t ntet);
 hipError_t launch_examples(const UniformArgs& P, int64_t first_cube, int64_t n_cubes, int min_cells,
                            float* feat, double* frac, uint8_t* mask, int64_t* tet_id,
                            int64_t capacity, void* ws, int64_t* n_out, hipStream_t stream);
+hipError_t launch_exact_fractions(const float* tets, double* frac, int64_t n, hipStream_t stream);
 hipError_t launch_surrogate_forward(const float* w, const float* feat, const uint8_t* mask, int64_t n,
                                     float* probs, hipStream_t stream);
 hipError_t launch_surrogate_backward(const float* w, const float* feat, const double* frac,

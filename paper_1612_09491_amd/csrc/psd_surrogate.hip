@@ -329,6 +329,87 @@ __device__ __forceinline__ double exact_fraction(const double (&vr)[4][3], const
     return inside_fraction<double, 0, 3>(x, k, ev);
 }
 
+// Exact fractions of given tetrahedra (vertices relative to the low corner
+// of a 2x2x2 block of cells, every coordinate in [0, 2)) in the block's 8
+// cells, cell c = 4 dx + 2 dy + dz.  A zero-volume tetrahedron (the rule of
+// the deposit, |D| <= 1e-12 l^3) puts everything in its centroid's cell;
+// vertices outside the block or non-finite give NaN in all 8 entries.
+__global__ __launch_bounds__(256) void exact_fractions_kernel(const float* tets, double* frac,
+                                                               int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double v[4][3];
+    bool ok = true;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            v[q][a] = (double)tets[(i * 4 + q) * 3 + a];
+            ok = ok && v[q][a] >= 0.0 && v[q][a] < 2.0;  // false for NaN
+        }
+    double* f = frac + i * kOut;
+    if (!ok) {
+#pragma unroll
+        for (int c = 0; c < kOut; ++c) f[c] = __builtin_nan("");
+        return;
+    }
+    double e[3][3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) e[m][a] = v[m + 1][a] - v[0][a];
+    const double D = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+                     e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                     e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+    double l2 = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int k = m + 1; k < 4; ++k) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) s += (v[m][a] - v[k][a]) * (v[m][a] - v[k][a]);
+            l2 = fmax(l2, s);
+        }
+    if (fabs(D) <= 1e-12 * l2 * sqrt(l2)) {
+        int cc = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double x = 0.25 * (v[0][a] + v[1][a] + v[2][a] + v[3][a]);
+            cc |= (x >= 1.0 ? 1 : 0) << (2 - a);
+        }
+#pragma unroll
+        for (int c = 0; c < kOut; ++c) f[c] = c == cc ? 1.0 : 0.0;
+        return;
+    }
+    // bbox origin lo (0 or 1 per axis) and span, then the cells inside it
+    double vr[4][3];
+    int lo[3], span[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double mn = fmin(fmin(v[0][a], v[1][a]), fmin(v[2][a], v[3][a]));
+        const double mx = fmax(fmax(v[0][a], v[1][a]), fmax(v[2][a], v[3][a]));
+        lo[a] = mn >= 1.0 ? 1 : 0;
+        span[a] = (mx >= 1.0 ? 1 : 0) - lo[a];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) vr[q][a] = v[q][a] - (double)lo[a];
+    }
+#pragma unroll
+    for (int c = 0; c < kOut; ++c) {
+        const int d[3] = {(c >> 2) & 1, (c >> 1) & 1, c & 1};
+        bool in = true;
+        int cl = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int r = d[a] - lo[a];
+            in = in && r >= 0 && r <= span[a];
+            cl |= (r & 1) << (2 - a);
+        }
+        f[c] = in ? exact_fraction(vr, span, cl) : 0.0;
+    }
+}
+
 struct ExampleArgs {
     const float* pos;
     int np[3];
@@ -951,6 +1032,14 @@ static int net_grid(int64_t n)
     const int64_t tiles = (n + 63) / 64;
     const int64_t cap = (int64_t)cus * 8;
     return (int)(tiles < cap ? (tiles > 0 ? tiles : 1) : cap);
+}
+
+hipError_t launch_exact_fractions(const float* tets, double* frac, int64_t n, hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(exact_fractions_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                       tets, frac, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_surrogate_forward(const float* w, const float* feat, const uint8_t* mask, int64_t n,

@@ -9,7 +9,10 @@
 - Adam: FP32 update against the FP64 reference, relative 1e-5;
 - deposit: the surrogate deposit equals the oracle's composition (exact for
   the other tetrahedra, the FP64 reference network for the eligible ones),
-  conserves mass, and counts the eligible tetrahedra.
+  conserves mass, and counts the eligible tetrahedra;
+- exact fractions of caller-given tetrahedra in a 2x2x2 block: the oracle's
+  polytope clipper within 1e-10, rows summing to 1, the zero-volume rule and
+  NaN rows for vertices outside the block.
 """
 
 import math
@@ -249,3 +252,60 @@ def test_training_gains_over_untrained_and_bbox_baseline(psd, orc):
     l1_dens_bbox = float(np.abs(base - exact).sum() / exact.sum())
     print(f"density L1: surrogate {l1_dens:.3e} bbox baseline {l1_dens_bbox:.3e}")
     assert l1_dens < 0.5 * l1_dens_bbox
+
+
+def _oracle_fractions(orc, tets):
+    """|T cap C_c| / |T| for the 8 cells of the block by the oracle's clipper."""
+    out = np.zeros((len(tets), 8))
+    for i, v in enumerate(tets.astype(np.float64)):
+        e = v[1:] - v[0]
+        vol = abs(np.linalg.det(e)) / 6.0
+        for c in range(8):
+            lo = np.array([(c >> 2) & 1, (c >> 1) & 1, c & 1], dtype=np.float64)
+            out[i, c] = orc.clip_tet_box(v, lo, lo + 1.0) / vol
+    return out
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.build_oracle(force=False)
+    return oracle
+
+
+def test_exact_fractions_match_oracle(psd, orc):
+    rng = np.random.default_rng(21)
+    big = rng.uniform(0.0, 2.0, (300, 4, 3))                      # up to all 8 cells
+    centre = rng.uniform(0.3, 1.7, (300, 1, 3))
+    small = centre + rng.normal(scale=0.25, size=(300, 4, 3))      # 1..8 cells
+    small = np.clip(small, 0.0, 1.999)
+    inside = rng.uniform(1.05, 1.95, (100, 4, 3))                  # one cell
+    base = rng.uniform(0.1, 1.9, (100, 3, 3))                      # slivers
+    w = rng.dirichlet([1, 1, 1], size=100)
+    sliver = np.concatenate([base, (np.einsum("nk,nkd->nd", w, base) +
+                                    rng.normal(scale=1e-3, size=(100, 3)))[:, None]], axis=1)
+    sliver = np.clip(sliver, 0.0, 1.999)
+    tets = np.concatenate([big, small, inside, sliver]).astype(np.float32)
+    got = psd.exact_fractions(torch.from_numpy(tets).cuda()).cpu().numpy()
+    ref = _oracle_fractions(orc, tets)
+    assert np.abs(got - ref).max() <= 1e-10
+    assert np.abs(got.sum(axis=1) - 1.0).max() <= 1e-12
+    # a tetrahedron inside one cell puts everything there
+    cell = (4 * (inside[:, 0, 0] >= 1) + 2 * (inside[:, 0, 1] >= 1) + (inside[:, 0, 2] >= 1)).astype(int)
+    assert np.array_equal(np.argmax(got[600:700], axis=1), cell)
+
+
+def test_exact_fractions_degenerate_and_outside(psd):
+    t = np.zeros((5, 4, 3), dtype=np.float32)
+    # zero volume (a repeated vertex): all in the centroid's cell (1, 0, 1) -> c = 5
+    t[0] = [[1.2, 0.3, 1.5], [1.6, 0.2, 1.1], [1.2, 0.3, 1.5], [1.4, 0.9, 1.3]]
+    t[1] = [[0.2, 0.3, 0.5], [2.0, 0.2, 0.1], [0.2, 0.9, 0.5], [0.4, 0.9, 0.3]]  # x = 2 is outside
+    t[2] = [[0.2, 0.3, 0.5], [0.6, 0.2, 0.1], [0.2, 0.9, 0.5], [-0.1, 0.9, 0.3]]
+    t[3] = [[0.2, 0.3, 0.5], [0.6, 0.2, np.nan], [0.2, 0.9, 0.5], [0.4, 0.9, 0.3]]
+    t[4] = [[0.2, 0.3, 0.5], [1.6, 0.2, 0.1], [0.2, 1.9, 0.5], [0.4, 0.9, 1.3]]
+    got = psd.exact_fractions(torch.from_numpy(t).cuda()).cpu().numpy()
+    assert np.array_equal(got[0], np.eye(8)[5])
+    assert np.isnan(got[1:4]).all()
+    assert np.isfinite(got[4]).all() and abs(got[4].sum() - 1.0) <= 1e-12
+    empty = psd.exact_fractions(torch.zeros((0, 4, 3), dtype=torch.float32, device="cuda"))
+    assert empty.shape == (0, 8)
