@@ -42,13 +42,8 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
 }
 
 // float -> bfloat16, round to nearest even (finite inputs).
-__device__ __forceinline__ __bf16 to_bf16(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    const unsigned short h = (unsigned short)(u >> 16);
-    return __builtin_bit_cast(__bf16, h);
-}
+// Round to nearest even (the hardware conversion, v_cvt_pk_bf16_f32).
+__device__ __forceinline__ __bf16 to_bf16(float f) { return (__bf16)f; }
 
 __device__ __forceinline__ float from_bf16(__bf16 h)
 {
@@ -67,7 +62,8 @@ __device__ __forceinline__ bf16x8 ld8s(const __bf16* p, int stride)
 
 __device__ __forceinline__ int wrap_cell(int x, int n) { return x >= n ? x - n : x; }
 
-__device__ __forceinline__ float sigmoid(float z) { return 1.0f / (1.0f + __expf(-z)); }
+// 1 / (1 + e^-z) with the hardware reciprocal (1 ulp; 0 when e^-z overflows).
+__device__ __forceinline__ float sigmoid(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 
 // Weight fragments of the A operand and bias columns, held per wave.
 // Lane l holds row (l & 15) of a 16-row tile, k = 8 (l >> 4) + 0..7.
