@@ -97,3 +97,14 @@ def test_deposit_rejects_bad_arguments_before_launch(psd):
     assert L.psd_deposit_uniform(fake, C.byref(p), nc, fake, None, C.byref(o), fake, 4096,
                                  None) == psd.PSD_ERR_ARG
     assert b"particle" in L.psd_last_error_detail()
+
+
+def test_launch_shape_validation(psd):
+    # buffer sizes are the kernel's instances; 0 means the defaults (960 entries,
+    # as many wavefronts as fit a compute unit)
+    for cap in (0, 512, 960, 2048):
+        assert psd.uniform_workspace_size((8, 8, 8), 16, tuning=(cap, 0, 0)) > 0
+    for bad in ((1024, 0, 0), (960, -1, 0), (960, 65, 0)):
+        with pytest.raises(psd.PsdError) as e:
+            psd.uniform_workspace_size((8, 8, 8), 16, tuning=bad)
+        assert e.value.code == psd.PSD_ERR_ARG
