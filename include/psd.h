@@ -73,9 +73,12 @@ typedef struct {
 /* Launch shape of the cumulative deposit (all zero = defaults). */
 typedef struct {
     int32_t lds_cap;      /* FP64 entries of the per-wavefront LDS buffer:
-                             512, 960 or 2048 (0 = 960)                       */
+                             512, 960 (16-tet groups), 1408 (8-tet groups) or
+                             2048; 0 = 1408 when every box has >= 1.5 grid
+                             cells per Lagrangian spacing (large tets), else
+                             960; octree leaves always 960                    */
     int32_t waves_per_cu; /* persistent wavefronts per compute unit (0 = as
-                             many as fit: 11 at 960 entries on gfx950)        */
+                             many as fit: 12 at 960 or 1408 entries on gfx950) */
     int32_t ordered;      /* 1: process 64-tet chunks in decreasing estimated
                              cost (bbox cells); 0: in index order             */
     int32_t reserved;     /* must be 0                                        */
@@ -158,9 +161,9 @@ psd_status psd_deposit_batched(const psd_box* boxes, int32_t n_boxes, double* ma
 
 /*
  * Chooses the launch shape (psd_tuning) of psd_deposit_batched for this batch
- * by timing candidates with HIP events on `stream`: LDS buffer of 960 or
- * 2048 FP64 entries, all the wavefronts that fit a compute unit or half of
- * them, chunks in index or cost order.  The boxes' outputs are overwritten with a valid deposit.  If
+ * by timing candidates with HIP events on `stream`: LDS buffer of 960, 1408
+ * or 2048 FP64 entries, all the wavefronts that fit a compute unit or half
+ * of them, chunks in index or cost order.  The boxes' outputs are overwritten with a valid deposit.  If
  * cache_path (host string, may be NULL) names a JSON file, a result for the
  * same device and batch signature is read from it instead of measuring, and
  * new results are added to it.  The workspace must be sized for ordered

@@ -74,7 +74,8 @@ bool tuning_ok(const psd_options* opt)
 {
     if (!opt || !opt->tuning) return true;
     const psd_tuning* u = opt->tuning;
-    return (u->lds_cap == 0 || u->lds_cap == 512 || u->lds_cap == 960 || u->lds_cap == 2048) &&
+    return (u->lds_cap == 0 || u->lds_cap == 512 || u->lds_cap == 960 || u->lds_cap == 1408 ||
+            u->lds_cap == 2048) &&
            u->waves_per_cu >= 0 && u->waves_per_cu <= 64 && u->reserved == 0;
 }
 

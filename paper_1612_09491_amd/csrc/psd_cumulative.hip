@@ -428,21 +428,22 @@ __device__ __forceinline__ void flush_mass(const BoxDesc& P, double& macc)
     macc = 0.0;
 }
 
-// A 64-tet chunk is built and walked in two halves of 32, which keeps the
-// LDS per wavefront near 13.7 KB at the default buffer (960 entries), so
-// that 11 wavefronts fit a compute unit; the launch bounds hold the
-// registers to three wavefronts per SIMD (two for the 2048-entry buffer,
-// whose LDS allows no more).
-constexpr int kHalf = kWave / 2;
-
-template <typename OutT, int CAP>
-__global__ __launch_bounds__(kWave, (CAP <= 960 ? 3 : 2)) void queue_kernel(QueueArgs Q)
+// A 64-tet chunk is built and walked in groups of GROUP tetrahedra: the tet
+// slots of a group and the D buffer of CAP FP64 entries share the LDS of a
+// wavefront.  Three wavefronts per SIMD (12 per compute unit) need at most
+// 13.6 KB of LDS each and at most 168 registers (the launch bounds); the
+// instances trade slots for buffer: 16 tets with 960 entries suit small
+// tetrahedra (many per batch), 8 tets with 1408 entries large ones (a few
+// fill the buffer).  The 2048-entry instance runs at two per SIMD.
+template <typename OutT, int CAP, int GROUP>
+__global__ __launch_bounds__(kWave, (CAP <= 1408 ? 3 : 2)) void queue_kernel(QueueArgs Q)
 {
-    __shared__ CTet slots[kHalf];
+    static_assert(kWave % GROUP == 0 && GROUP <= kWave, "chunk of whole groups");
+    __shared__ CTet slots[GROUP];
     __shared__ double Dbuf[CAP];
-    __shared__ Tile tiles[kHalf];
-    __shared__ int t_slot[kHalf];
-    __shared__ int64_t s_incl[kHalf];
+    __shared__ Tile tiles[GROUP];
+    __shared__ int t_slot[GROUP];
+    __shared__ int64_t s_incl[GROUP];
     __shared__ int64_t s_item;
 
     const int lane = threadIdx.x;
@@ -477,26 +478,26 @@ __global__ __launch_bounds__(kWave, (CAP <= 960 ? 3 : 2)) void queue_kernel(Queu
         }
         OutT* out = reinterpret_cast<OutT*>(P.out);
 
-        for (int half = 0; half < 2; ++half) {
-        const int q = half * kHalf + lane;  // tet of the chunk
+        for (int grp = 0; grp < kWave / GROUP; ++grp) {
+        const int q = grp * GROUP + lane;  // tet of the chunk
         const int64_t tid = (g - P.chunk_begin) * kWave + q;
         int ncell = 0;
-        if (lane < kHalf && tid < P.ntet) {
+        if (lane < GROUP && tid < P.ntet) {
             ++n_tet;
             // tets already deposited by the surrogate are not built again
             const bool mine = !P.exact_mask || ((P.exact_mask[g - P.chunk_begin] >> q) & 1ull);
             if (mine) ncell = setup_tet<OutT>(P, tid, slots[lane], macc, n_pair, n_nz, n_inv, n_deg);
         }
-        if (lane < kHalf) slots[lane].ncell = ncell;
+        if (lane < GROUP) slots[lane].ncell = ncell;
         __syncthreads();
 
-        // Walk the half's tetrahedra in tile batches that fit the D buffer.
+        // Walk the group's tetrahedra in tile batches that fit the D buffer.
         int cur = 0;       // next slot to start
         int cur_tile = 0;  // for a tiled tetrahedron, linear index of its next tile
-        while (cur < kHalf) {
+        while (cur < GROUP) {
             // Wave-uniform planning (every lane computes the same list).
             int nt = 0, used = 0;
-            while (cur < kHalf && nt < kHalf) {
+            while (cur < GROUP && nt < GROUP) {
                 const CTet& S = slots[cur];
                 if (S.ncell == 0) {
                     ++cur;
@@ -552,7 +553,7 @@ __global__ __launch_bounds__(kWave, (CAP <= 960 ? 3 : 2)) void queue_kernel(Queu
                     const int64_t y = __shfl_up(incl, off, kWave);
                     if (lane >= off) incl += y;
                 }
-                if (lane < kHalf) s_incl[lane] = incl;  // nt <= kHalf
+                if (lane < GROUP) s_incl[lane] = incl;  // nt <= GROUP
                 __syncthreads();
                 const int64_t total = __shfl(incl, kWave - 1, kWave);
                 for (int64_t base = 0; base < total; base += kWave) {
@@ -748,23 +749,27 @@ QueueLayout queue_layout(int64_t n_chunks, int n_boxes, bool ordered)
     return L;
 }
 
+// Kernel instances by buffer size: (entries, tets per group).
 template <typename OutT>
 const void* queue_kernel_for(int cap)
 {
-    if (cap <= 512) return reinterpret_cast<const void*>(&queue_kernel<OutT, 512>);
-    if (cap <= 960) return reinterpret_cast<const void*>(&queue_kernel<OutT, 960>);
-    return reinterpret_cast<const void*>(&queue_kernel<OutT, 2048>);
+    if (cap <= 512) return reinterpret_cast<const void*>(&queue_kernel<OutT, 512, 16>);
+    if (cap <= 960) return reinterpret_cast<const void*>(&queue_kernel<OutT, 960, 16>);
+    if (cap <= 1408) return reinterpret_cast<const void*>(&queue_kernel<OutT, 1408, 8>);
+    return reinterpret_cast<const void*>(&queue_kernel<OutT, 2048, 32>);
 }
 
 template <typename OutT>
 hipError_t launch_queue_kernel(const QueueArgs& Q, int cap, int grid, hipStream_t stream)
 {
     if (cap <= 512)
-        hipLaunchKernelGGL((queue_kernel<OutT, 512>), dim3(grid), dim3(kWave), 0, stream, Q);
+        hipLaunchKernelGGL((queue_kernel<OutT, 512, 16>), dim3(grid), dim3(kWave), 0, stream, Q);
     else if (cap <= 960)
-        hipLaunchKernelGGL((queue_kernel<OutT, 960>), dim3(grid), dim3(kWave), 0, stream, Q);
+        hipLaunchKernelGGL((queue_kernel<OutT, 960, 16>), dim3(grid), dim3(kWave), 0, stream, Q);
+    else if (cap <= 1408)
+        hipLaunchKernelGGL((queue_kernel<OutT, 1408, 8>), dim3(grid), dim3(kWave), 0, stream, Q);
     else
-        hipLaunchKernelGGL((queue_kernel<OutT, 2048>), dim3(grid), dim3(kWave), 0, stream, Q);
+        hipLaunchKernelGGL((queue_kernel<OutT, 2048, 32>), dim3(grid), dim3(kWave), 0, stream, Q);
     return hipGetLastError();
 }
 
@@ -773,18 +778,32 @@ hipError_t launch_queue_kernel(const QueueArgs& Q, int cap, int grid, hipStream_
 Tuning default_tuning()
 {
     Tuning t;
-    t.cap = 960;
+    t.cap = 0;           // chosen from the boxes (auto_cap)
     t.waves_per_cu = 0;  // as many as fit a compute unit
     t.ordered = 0;
     return t;
+}
+
+int auto_cap(const BoxDesc* boxes, int n_boxes)
+{
+    // Grid cells per Lagrangian spacing: from about 1.5 on, tetrahedra span
+    // hundreds of cells and a few of them fill the buffer; octree levels
+    // always hold small ones.
+    double ratio = 1e30;
+    for (int b = 0; b < n_boxes; ++b) {
+        if (boxes[b].leaf_map) return 960;
+        for (int a = 0; a < 3; ++a)
+            ratio = fmin(ratio, (double)boxes[b].nc[a] / (double)boxes[b].np[a]);
+    }
+    return ratio >= 1.5 ? 1408 : 960;
 }
 
 hipError_t queue_resident_waves(int cap, bool out_fp64, int& waves)
 {
     // one kernel instance per (buffer size, output type); the answer only
     // depends on the instance, so it is asked once
-    static std::atomic<int> known[3][2];
-    const int ci = cap <= 512 ? 0 : (cap <= 960 ? 1 : 2), ti = out_fp64 ? 1 : 0;
+    static std::atomic<int> known[4][2];
+    const int ci = cap <= 512 ? 0 : (cap <= 960 ? 1 : (cap <= 1408 ? 2 : 3)), ti = out_fp64 ? 1 : 0;
     int n = known[ci][ti].load(std::memory_order_relaxed);
     if (n == 0) {
         const void* k = out_fp64 ? queue_kernel_for<double>(cap) : queue_kernel_for<float>(cap);
@@ -859,16 +878,17 @@ hipError_t launch_queue(const BoxDesc* boxes_in, int n_boxes, bool out_fp64, con
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         cus < 1)
         cus = 256;
+    const int cap = tune.cap > 0 ? tune.cap : auto_cap(boxes.data(), n_boxes);
     int waves = tune.waves_per_cu;
     if (waves <= 0) {
-        const hipError_t e = queue_resident_waves(tune.cap, out_fp64, waves);
+        const hipError_t e = queue_resident_waves(cap, out_fp64, waves);
         if (e != hipSuccess) return e;
     }
     int64_t grid = (int64_t)cus * waves;
     if (grid > n_chunks) grid = n_chunks;
     if (grid < 1) grid = 1;
-    return out_fp64 ? launch_queue_kernel<double>(Q, tune.cap, (int)grid, stream)
-                    : launch_queue_kernel<float>(Q, tune.cap, (int)grid, stream);
+    return out_fp64 ? launch_queue_kernel<double>(Q, cap, (int)grid, stream)
+                    : launch_queue_kernel<float>(Q, cap, (int)grid, stream);
 }
 
 }  // namespace psd

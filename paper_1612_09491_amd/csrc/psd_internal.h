@@ -66,7 +66,8 @@ struct BoxDesc {
 };
 
 struct Tuning {
-    int cap;            // FP64 entries of the per-wave LDS buffer: 512, 960 or 2048
+    int cap;            // FP64 entries of the per-wave LDS buffer: 512, 960, 1408 or 2048
+                        // (0: chosen from the boxes' cells per Lagrangian spacing)
     int waves_per_cu;   // persistent workgroups per compute unit (0: as many as fit)
     int ordered;        // 1: chunks in decreasing estimated cost
 };
