@@ -335,6 +335,22 @@ __device__ __forceinline__ int box_of(const QueueArgs& Q, int64_t g)
     return lo;
 }
 
+// Position of the k-th set bit (k from 0, k < popcount(m)) of m.
+__device__ __forceinline__ int nth_bit(uint64_t m, int k)
+{
+    int pos = 0;
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const uint64_t low = (1ull << w) - 1ull;
+        const int c = __popcll(m & low);
+        const bool up = k >= c;
+        k = up ? k - c : k;
+        m = up ? m >> w : m & low;
+        pos += up ? w : 0;
+    }
+    return pos;
+}
+
 // Builds tetrahedron `tid` of box P into slot S; returns its bbox cell count
 // (0 when nothing is left to do) and deposits the cases that need no walk.
 template <typename OutT>
@@ -478,15 +494,20 @@ __global__ __launch_bounds__(kWave, (CAP <= 1408 ? 3 : 2)) void queue_kernel(Que
         }
         OutT* out = reinterpret_cast<OutT*>(P.out);
 
-        for (int grp = 0; grp < kWave / GROUP; ++grp) {
-        const int q = grp * GROUP + lane;  // tet of the chunk
-        const int64_t tid = (g - P.chunk_begin) * kWave + q;
+        // The chunk's tets to deposit: all of them, or those the surrogate
+        // left (its mask), taken in order GROUP at a time.
+        const int64_t first = (g - P.chunk_begin) * kWave;
+        const int64_t left = P.ntet - first;
+        const int nvalid = left < kWave ? (int)left : kWave;
+        if (lane == 0) n_tet += nvalid;
+        const uint64_t todo = P.exact_mask ? P.exact_mask[g - P.chunk_begin] : 0ull;
+        const int ntodo = P.exact_mask ? __popcll(todo) : nvalid;
+        for (int grp = 0; grp * GROUP < ntodo; ++grp) {
+        const int k = grp * GROUP + lane;  // rank among the chunk's tets to do
         int ncell = 0;
-        if (lane < GROUP && tid < P.ntet) {
-            ++n_tet;
-            // tets already deposited by the surrogate are not built again
-            const bool mine = !P.exact_mask || ((P.exact_mask[g - P.chunk_begin] >> q) & 1ull);
-            if (mine) ncell = setup_tet<OutT>(P, tid, slots[lane], macc, n_pair, n_nz, n_inv, n_deg);
+        if (lane < GROUP && k < ntodo) {
+            const int64_t tid = first + (P.exact_mask ? nth_bit(todo, k) : k);
+            ncell = setup_tet<OutT>(P, tid, slots[lane], macc, n_pair, n_nz, n_inv, n_deg);
         }
         if (lane < GROUP) slots[lane].ncell = ncell;
         __syncthreads();
