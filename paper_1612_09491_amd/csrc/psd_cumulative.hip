@@ -17,9 +17,9 @@
 // Work: persistent single-wavefront workgroups pop 64-tetrahedron chunks
 // from a device counter (optionally in decreasing order of estimated cost)
 // over a table of independent boxes -- one periodic grid, the levels of an
-// octree, or a batch of uneven boxes.  Per chunk, lanes build 64 tetrahedra
-// into LDS; small ones are batched so that their D arrays share an LDS
-// buffer, larger ones are tiled.  (tet, column) pairs go over the lanes 64
+// octree, or a batch of uneven boxes.  Per chunk, lanes build the
+// tetrahedra into LDS a group at a time; small ones are batched so that
+// their D arrays share an LDS buffer, larger ones are tiled.  (tet, column) pairs go over the lanes 64
 // at a time: phase 1 fills a window's D columns, phase 2 then walks the
 // cells of the same columns, takes the differences and scatters the
 // non-zero cell masses with global atomics.
