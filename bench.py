@@ -37,7 +37,9 @@ METRIC = "tetrahedra deposited/sec on 1 MI355X, exact vs surrogate at stated den
 WORKLOAD = "zel256_g512"
 
 # VALU issue rate: 256 CUs x 64 lanes x 2.4 GHz (one lane-op per lane per clock).
-PEAK_VALU_OPS = 256 * 64 * 2.4e9
+SIMDS = 256 * 4            # compute units x SIMDs, MI355X
+CLOCK_HZ = 2.4e9           # peak engine clock
+PEAK_VALU_OPS = 256 * 64 * CLOCK_HZ
 
 # Unit costs (lane-ops) of the paper's method, per counted event: tetrahedron
 # setup, bbox-cell classification, signed distance per vertex per plane visit,
@@ -491,6 +493,11 @@ def main() -> int:
             "kernel_ms": kernel_ms,
             "algorithmic_ops_per_tet": ops_per_tet,
         }
+        if traffic and traffic.get("valu_insts_per_launch"):
+            # machine view of the same launch: wave64 VALU instructions (rocprofv3
+            # SQ_INSTS_VALU of this kernel version) x 4 clocks over 1024 SIMDs
+            roofline["valu_issue_frac"] = (4.0 * traffic["valu_insts_per_launch"] /
+                                           (SIMDS * CLOCK_HZ * kernel_ms / 1e3))
 
     line = {
         "metric": METRIC,
