@@ -184,11 +184,14 @@ __device__ __forceinline__ void lds_add(double* p, double v)
 }
 
 // Adds frac * (share of each z-cell of the tile) for one piece.  The levels
-// are walked region by region of the piecewise cubic, so each step evaluates
-// one cubic only; every cubic is scaled by frac up front.  On (s1, s2) the
-// cubic is expanded in t = k - s1: each expanded term is bounded by 1 there
-// (t <= s2 - s1 <= s3 - s1 and s1 - s0 <= s2 - s0, s3 - s0), so Horner's
-// rule loses only a few ulps.
+// are walked region by region of the piecewise cubic; every cubic is scaled
+// by frac up front.  On (s1, s2) the cubic is expanded in t = k - s1: each
+// expanded term is bounded by 1 there (t <= s2 - s1 <= s3 - s1 and
+// s1 - s0 <= s2 - s0, s3 - s0), so Horner's rule loses only a few ulps.
+// Inside a region a level's share is the cubic's difference over a unit
+// step, a quadratic evaluated directly (nothing is carried from level to
+// level, so no error accumulates); the end regions' quadratics have only
+// positive terms.
 __device__ __forceinline__ void spread_z(const double z[4], double frac, const Tile& t,
                                          double* Dcol)
 {
@@ -202,35 +205,64 @@ __device__ __forceinline__ void spread_z(const double z[4], double frac, const T
     double* p = Dcol + (lA - t.l0);
     double k = (double)(lA + 1);       // upper plane of the level
     const double kB = (double)(lB + 1);
-    // k <= s1
+    // Each region: its first level from F at both planes (the lower plane
+    // may lie in the region before), the others from the difference of the
+    // region's cubic over a unit step, a quadratic in the upper plane.
+    // k <= s1: F = fA u^3, u = k - s0; step fA (3u^2 - 3u + 1), u >= 1
     const double fA = frac * Z.iA;
     const double kLow = fmin(Z.s1, kB);
-    for (; k <= kLow; k += 1.0, ++p) {
-        const double u = k - Z.s0;
-        const double F = fA * (u * u * u);
-        lds_add(p, F - Fprev);
-        Fprev = F;
+    if (k <= kLow) {
+        double u = k - Z.s0;
+        lds_add(p, fA * (u * u * u) - Fprev);
+        k += 1.0;
+        ++p;
+        const double g = 3.0 * fA;
+        for (; k <= kLow; k += 1.0, ++p) {
+            u = k - Z.s0;
+            lds_add(p, fma(u, fma(g, u, -g), fA));
+        }
+        u = (k - 1.0) - Z.s0;
+        Fprev = fA * (u * u * u);
     }
-    // s1 < k < s2
-    const double a = Z.s1 - Z.s0;
-    const double A = Z.r20 * Z.r30, B = Z.r20 * Z.r31;
-    const double c0 = frac * (A * a * a);
-    const double c1 = frac * (a * (A * (2.0 - Z.r31 * a) + B));
-    const double c2 = frac * (A * (1.0 - 2.0 * a * Z.r31) + B * (1.0 - a * Z.r21) + Z.r21 * Z.r31);
-    const double c3 = -frac * (A * Z.r31 + B * Z.r21);
-    for (; k < Z.s2 && k <= kB; k += 1.0, ++p) {
-        const double tt = k - Z.s1;
-        const double F = fma(fma(fma(c3, tt, c2), tt, c1), tt, c0);
-        lds_add(p, F - Fprev);
-        Fprev = F;
+    // s1 < k < s2: F = c0 + c1 t + c2 t^2 + c3 t^3, t = k - s1;
+    // step q0 + q1 t + q2 t^2
+    if (k < Z.s2 && k <= kB) {
+        const double a = Z.s1 - Z.s0;
+        const double A = Z.r20 * Z.r30, B = Z.r20 * Z.r31;
+        const double c0 = frac * (A * a * a);
+        const double c1 = frac * (a * (A * (2.0 - Z.r31 * a) + B));
+        const double c2 = frac * (A * (1.0 - 2.0 * a * Z.r31) + B * (1.0 - a * Z.r21) + Z.r21 * Z.r31);
+        const double c3 = -frac * (A * Z.r31 + B * Z.r21);
+        double tt = k - Z.s1;
+        lds_add(p, fma(fma(fma(c3, tt, c2), tt, c1), tt, c0) - Fprev);
+        k += 1.0;
+        ++p;
+        const double q0 = c1 - c2 + c3, q1 = 2.0 * c2 - 3.0 * c3, q2 = 3.0 * c3;
+        for (; k < Z.s2 && k <= kB; k += 1.0, ++p) {
+            tt = k - Z.s1;
+            lds_add(p, fma(fma(q2, tt, q1), tt, q0));
+        }
+        tt = (k - 1.0) - Z.s1;
+        Fprev = fma(fma(fma(c3, tt, c2), tt, c1), tt, c0);
     }
-    // s2 <= k; the last level's upper plane lies above s3
-    const double fC = frac * Z.iC;
-    for (; k <= kB; k += 1.0, ++p) {
-        const double w = Z.s3 - k;
-        const double F = w > 0.0 ? frac - fC * (w * w * w) : frac;
-        lds_add(p, F - Fprev);
-        Fprev = F;
+    // s2 <= k: F = frac - fC w^3, w = s3 - k (frac once k >= s3);
+    // step fC (3w^2 + 3w + 1) while k < s3
+    if (k <= kB) {
+        const double fC = frac * Z.iC;
+        double w = Z.s3 - k;
+        lds_add(p, (w > 0.0 ? frac - fC * (w * w * w) : frac) - Fprev);
+        k += 1.0;
+        ++p;
+        const double g = 3.0 * fC;
+        for (; k < Z.s3 && k <= kB; k += 1.0, ++p) {
+            w = Z.s3 - k;
+            lds_add(p, fma(w, fma(g, w, g), fC));
+        }
+        // the level whose upper plane passes s3
+        if (k <= kB) {
+            w = Z.s3 - (k - 1.0);
+            lds_add(p, fC * (w * w * w));
+        }
     }
 }
 
