@@ -155,10 +155,14 @@ __device__ __forceinline__ void zdist_init(const double z[4], ZDist& Z)
     Z.s3 = s3;
     const double d10 = Z.s1 - s0, d20 = Z.s2 - s0, d30 = s3 - s0;
     const double d21 = Z.s2 - Z.s1, d31 = s3 - Z.s1, d32 = s3 - Z.s2;
-    Z.r20 = rcp_or0(d20);
-    Z.r30 = rcp_or0(d30);
-    Z.r21 = rcp_or0(d21);
-    Z.r31 = rcp_or0(d31);
+    // the middle region's four reciprocals from one: all four differences
+    // are positive whenever that region is not empty (else they are unused)
+    const double P1 = d20 * d30, P2 = d21 * d31;
+    const double R = rcp_or0(P1 * P2);
+    Z.r20 = d30 * P2 * R;
+    Z.r30 = d20 * P2 * R;
+    Z.r21 = P1 * d31 * R;
+    Z.r31 = P1 * d21 * R;
     Z.iA = rcp_or0(d10 * d20 * d30);
     Z.iC = rcp_or0(d30 * d31 * d32);
 }
