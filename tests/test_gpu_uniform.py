@@ -207,3 +207,20 @@ def test_zel256_g512_sampled_blocks(psd, orc, method):
         l1 = _rel_l1(blk, ref)
         print(f"block {lo}: L1 {l1:.3e} Linf {_rel_linf(blk, ref):.3e}")
         assert l1 <= FP32_L1
+
+
+@pytest.mark.parametrize("nc", [64, 20])
+def test_kernel_instances_agree(psd, orc, nc):
+    # 32^3 particles onto 64^3 (2 cells per spacing: the default is the 1408-entry
+    # buffer with 8-tet groups) and onto 20^3 (0.6: 960 entries, 16-tet groups);
+    # every instance and launch shape gives the oracle's grid in FP64
+    pos = zeldovich_positions(32, 0.5, seed=9)
+    ref, _ = orc.deposit_uniform(pos, nc)
+    dev = torch.device("cuda:0")
+    pt = torch.from_numpy(pos).to(dev)
+    for tuning in (None, (512, 0, 0), (960, 12, 1), (1408, 12, 0), (2048, 7, 0), (1408, 3, 1)):
+        ms = torch.zeros(1, dtype=torch.float64, device=dev)
+        out = psd.deposit_uniform(pt, nc, flags=psd.PSD_PREC_FP64, mass_sum=ms, tuning=tuning)
+        got = out.cpu().numpy()
+        assert _rel_l1(got, ref) <= FP64_L1, (tuning, _rel_l1(got, ref))
+        assert abs(float(ms.item()) - 1.0) <= 1e-12
