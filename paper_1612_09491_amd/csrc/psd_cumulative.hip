@@ -553,8 +553,51 @@ __global__ __launch_bounds__(kWave, (CAP <= 1408 ? 3 : 2)) void queue_kernel(Que
         int cur_tile = 0;  // for a tiled tetrahedron, linear index of its next tile
         while (cur < GROUP) {
             // Wave-uniform planning (every lane computes the same list).
+            // With 16-tet groups (small tets, many per batch) runs of
+            // untiled tetrahedra are laid out by all lanes at once: one slot
+            // per lane and a scan of their D sizes.
             int nt = 0, used = 0;
             while (cur < GROUP && nt < GROUP) {
+                if constexpr (GROUP >= 16) {
+                    if (cur_tile == 0 && slots[cur].ncell <= CAP) {
+                        const int s = cur + lane;
+                        const int nc = s < GROUP ? slots[s].ncell : 0;
+                        const uint64_t tiled = __ballot(s < GROUP && nc > CAP);
+                        const int lim = tiled ? __ffsll((long long)tiled) - 1 : GROUP - cur;
+                        const int ds = lane < lim ? nc : 0;  // an untiled tile's D size is its cells
+                        int incl = ds;
+#pragma unroll
+                        for (int off = 1; off < kWave; off <<= 1) {
+                            const int y = __shfl_up(incl, off, kWave);
+                            if (lane >= off) incl += y;
+                        }
+                        const uint64_t busy = __ballot(ds > 0);
+                        const uint64_t upto = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull);
+                        const int rank = __popcll(busy & upto);  // tiles up to this slot
+                        // a prefix of the lanes: each condition is monotone in the lane
+                        const bool take = lane < lim && used + incl <= CAP && nt + rank <= GROUP;
+                        const int ntake = __popcll(__ballot(take));
+                        if (take && ds > 0) {
+                            const CTet& S = slots[s];
+                            Tile t;
+                            t.a0 = 0; t.ta = S.ext[0]; t.b0 = 0; t.tb = S.ext[1];
+                            t.l0 = 0; t.tl = S.ext[2]; t.ha = 0; t.hb = 0;
+                            t.doff = used + incl - ds;
+                            t.inv_wb = 1.0f / (float)t.tb;
+                            t.inv_tb = t.inv_wb;
+                            t.inv_tl = 1.0f / (float)t.tl;
+                            tiles[nt + rank - 1] = t;
+                            t_slot[nt + rank - 1] = s;
+                        }
+                        if (ntake > 0) {
+                            nt += __shfl(rank, ntake - 1, kWave);
+                            used += __shfl(incl, ntake - 1, kWave);
+                            cur += ntake;
+                        }
+                        if (ntake < lim) break;  // buffer or tile list full
+                        continue;
+                    }
+                }
                 const CTet& S = slots[cur];
                 if (S.ncell == 0) {
                     ++cur;
