@@ -135,6 +135,21 @@ def test_huge_stretched_tets(psd, orc):
     _compare(psd, orc, pos, 48)
 
 
+@pytest.mark.parametrize("tuning", [(512, 0, 0), (960, 0, 1), (1408, 0, 0), (2048, 0, 0)])
+def test_huge_tets_tiled_in_every_instance(psd, orc, tuning):
+    # tets of thousands of bbox cells are tiled with halo columns; in the 16-tet
+    # instances they also interrupt the all-lanes planning of untiled runs
+    pos = zeldovich_positions(4, 1.4, seed=44)
+    ref, _ = orc.deposit_uniform(pos, 48)
+    dev = torch.device("cuda:0")
+    pt = torch.from_numpy(pos).to(dev)
+    st = torch.zeros(8, dtype=torch.int64, device=dev)
+    out = psd.deposit_uniform(pt, 48, flags=psd.PSD_PREC_FP64, stats=st, tuning=tuning)
+    assert _rel_l1(out.cpu().numpy(), ref) <= FP64_L1
+    # more cells than the buffer in some tetrahedron: the tiled walk ran
+    assert int(st[1].item()) > 0
+
+
 def test_flat_tets_go_to_centroid_cell(psd, orc):
     pos = lattice_positions(8).astype(np.float64)
     pos[:, :, :, 2] = 0.3
