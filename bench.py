@@ -107,8 +107,9 @@ def cpu_baseline(pos: np.ndarray, nc: int, gpu_grid: np.ndarray | None, n_cubes:
     return out
 
 
-# tets per group of each deposit-kernel instance (LDS buffer entries -> group)
-GROUP_OF_CAP = {512: 16, 960: 16, 1408: 8, 2048: 32}
+# template arguments after the buffer size of each deposit-kernel instance:
+# tets set up at once, tiles per batch
+GROUP_OF_CAP = {512: "16, 16", 960: "32, 16", 1408: "8, 8", 2048: "32, 32"}
 
 SURROGATE_WEIGHTS = os.path.join(ROOT, "paper_1612_09491_amd", "surrogate_zel256_g64.npy")
 
@@ -267,7 +268,7 @@ def bench_octree(args, torch, psd) -> dict:
         line["roofline"] = {"bound": "alu", "achieved": achieved / 1e12,
                             "peak": PEAK_VALU_OPS / 1e12, "unit": "Top/s",
                             "frac": achieved / PEAK_VALU_OPS, "traffic": None,
-                            "kernel": "queue_kernel<float, 960, 16>", "kernel_ms": kernel_ms,
+                            "kernel": "queue_kernel<float, 960, 32, 16>", "kernel_ms": kernel_ms,
                             "algorithmic_ops_per_tet": o["ops_per_tet"]}
     return line
 
@@ -489,7 +490,7 @@ def main() -> int:
             "unit": "Top/s",
             "frac": achieved / PEAK_VALU_OPS,
             "traffic": traffic["bytes_per_launch"] if traffic else None,
-            "kernel": "queue_kernel<float, 1408, 8>",
+            "kernel": "queue_kernel<float, 1408, 8, 8>",
             "kernel_ms": kernel_ms,
             "algorithmic_ops_per_tet": ops_per_tet,
         }

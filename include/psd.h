@@ -73,8 +73,9 @@ typedef struct {
 /* Launch shape of the cumulative deposit (all zero = defaults). */
 typedef struct {
     int32_t lds_cap;      /* FP64 entries of the per-wavefront LDS buffer:
-                             512, 960 (16-tet groups), 1408 (8-tet groups) or
-                             2048; 0 = 1408 when every box has >= 1.5 grid
+                             512 (16-tet groups), 960 (32 tets set up at
+                             once, 16 tiles a batch), 1408 (8-tet groups) or
+                             2048 (32-tet groups); 0 = 1408 when every box has >= 1.5 grid
                              cells per Lagrangian spacing (large tets), else
                              960; octree leaves always 960                    */
     int32_t waves_per_cu; /* persistent wavefronts per compute unit (0 = as

@@ -480,22 +480,24 @@ __device__ __forceinline__ void flush_mass(const BoxDesc& P, double& macc)
     macc = 0.0;
 }
 
-// A 64-tet chunk is built and walked in groups of GROUP tetrahedra: the tet
-// slots of a group and the D buffer of CAP FP64 entries share the LDS of a
-// wavefront.  Three wavefronts per SIMD (12 per compute unit) need at most
-// 13.6 KB of LDS each and at most 168 registers (the launch bounds); the
-// instances trade slots for buffer: 16 tets with 960 entries suit small
-// tetrahedra (many per batch), 8 tets with 1408 entries large ones (a few
-// fill the buffer).  The 2048-entry instance runs at two per SIMD.
-template <typename OutT, int CAP, int GROUP>
+// A 64-tet chunk is built in groups of GROUP tetrahedra (one per lane) and
+// each group is walked in batches of at most TILES tiles: the tet slots of a
+// group and the D buffer of CAP FP64 entries share the LDS of a wavefront.
+// Three wavefronts per SIMD (12 per compute unit) need at most 13.6 KB of
+// LDS each and at most 168 registers (the launch bounds); the instances
+// trade slots for buffer: 32 tets set up at once with 960 entries and 16
+// tiles a batch suit small tetrahedra (many per batch), 8 tets with 1408
+// entries large ones (a few fill the buffer).  The 2048-entry instance runs
+// at two per SIMD.
+template <typename OutT, int CAP, int GROUP, int TILES>
 __global__ __launch_bounds__(kWave, (CAP <= 1408 ? 3 : 2)) void queue_kernel(QueueArgs Q)
 {
-    static_assert(kWave % GROUP == 0 && GROUP <= kWave, "chunk of whole groups");
+    static_assert(kWave % GROUP == 0 && GROUP <= kWave && TILES <= GROUP, "chunk of whole groups");
     __shared__ CTet slots[GROUP];
     __shared__ double Dbuf[CAP];
-    __shared__ Tile tiles[GROUP];
-    __shared__ int t_slot[GROUP];
-    __shared__ int64_t s_incl[GROUP];
+    __shared__ Tile tiles[TILES];
+    __shared__ int t_slot[TILES];
+    __shared__ int64_t s_incl[TILES];
     __shared__ int64_t s_item;
 
     const int lane = threadIdx.x;
@@ -557,7 +559,7 @@ __global__ __launch_bounds__(kWave, (CAP <= 1408 ? 3 : 2)) void queue_kernel(Que
             // untiled tetrahedra are laid out by all lanes at once: one slot
             // per lane and a scan of their D sizes.
             int nt = 0, used = 0;
-            while (cur < GROUP && nt < GROUP) {
+            while (cur < GROUP && nt < TILES) {
                 if constexpr (GROUP >= 16) {
                     if (cur_tile == 0 && slots[cur].ncell <= CAP) {
                         const int s = cur + lane;
@@ -575,7 +577,7 @@ __global__ __launch_bounds__(kWave, (CAP <= 1408 ? 3 : 2)) void queue_kernel(Que
                         const uint64_t upto = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull);
                         const int rank = __popcll(busy & upto);  // tiles up to this slot
                         // a prefix of the lanes: each condition is monotone in the lane
-                        const bool take = lane < lim && used + incl <= CAP && nt + rank <= GROUP;
+                        const bool take = lane < lim && used + incl <= CAP && nt + rank <= TILES;
                         const int ntake = __popcll(__ballot(take));
                         if (take && ds > 0) {
                             const CTet& S = slots[s];
@@ -653,7 +655,7 @@ __global__ __launch_bounds__(kWave, (CAP <= 1408 ? 3 : 2)) void queue_kernel(Que
                     const int64_t y = __shfl_up(incl, off, kWave);
                     if (lane >= off) incl += y;
                 }
-                if (lane < GROUP) s_incl[lane] = incl;  // nt <= GROUP
+                if (lane < TILES) s_incl[lane] = incl;  // nt <= TILES
                 __syncthreads();
                 const int64_t total = __shfl(incl, kWave - 1, kWave);
                 for (int64_t base = 0; base < total; base += kWave) {
@@ -853,23 +855,23 @@ QueueLayout queue_layout(int64_t n_chunks, int n_boxes, bool ordered)
 template <typename OutT>
 const void* queue_kernel_for(int cap)
 {
-    if (cap <= 512) return reinterpret_cast<const void*>(&queue_kernel<OutT, 512, 16>);
-    if (cap <= 960) return reinterpret_cast<const void*>(&queue_kernel<OutT, 960, 16>);
-    if (cap <= 1408) return reinterpret_cast<const void*>(&queue_kernel<OutT, 1408, 8>);
-    return reinterpret_cast<const void*>(&queue_kernel<OutT, 2048, 32>);
+    if (cap <= 512) return reinterpret_cast<const void*>(&queue_kernel<OutT, 512, 16, 16>);
+    if (cap <= 960) return reinterpret_cast<const void*>(&queue_kernel<OutT, 960, 32, 16>);
+    if (cap <= 1408) return reinterpret_cast<const void*>(&queue_kernel<OutT, 1408, 8, 8>);
+    return reinterpret_cast<const void*>(&queue_kernel<OutT, 2048, 32, 32>);
 }
 
 template <typename OutT>
 hipError_t launch_queue_kernel(const QueueArgs& Q, int cap, int grid, hipStream_t stream)
 {
     if (cap <= 512)
-        hipLaunchKernelGGL((queue_kernel<OutT, 512, 16>), dim3(grid), dim3(kWave), 0, stream, Q);
+        hipLaunchKernelGGL((queue_kernel<OutT, 512, 16, 16>), dim3(grid), dim3(kWave), 0, stream, Q);
     else if (cap <= 960)
-        hipLaunchKernelGGL((queue_kernel<OutT, 960, 16>), dim3(grid), dim3(kWave), 0, stream, Q);
+        hipLaunchKernelGGL((queue_kernel<OutT, 960, 32, 16>), dim3(grid), dim3(kWave), 0, stream, Q);
     else if (cap <= 1408)
-        hipLaunchKernelGGL((queue_kernel<OutT, 1408, 8>), dim3(grid), dim3(kWave), 0, stream, Q);
+        hipLaunchKernelGGL((queue_kernel<OutT, 1408, 8, 8>), dim3(grid), dim3(kWave), 0, stream, Q);
     else
-        hipLaunchKernelGGL((queue_kernel<OutT, 2048, 32>), dim3(grid), dim3(kWave), 0, stream, Q);
+        hipLaunchKernelGGL((queue_kernel<OutT, 2048, 32, 32>), dim3(grid), dim3(kWave), 0, stream, Q);
     return hipGetLastError();
 }
 
