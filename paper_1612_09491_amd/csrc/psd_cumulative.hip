@@ -93,7 +93,9 @@ __device__ __forceinline__ int64_t out_index(const BoxDesc& P, int x, int y, int
 {
     if (!P.leaf_map) return ((int64_t)x * P.nc[1] + y) * P.nc[2] + z;
     const int B = P.leaf_block, side = P.leaf_side;
-    const int nx = x / B, ny = y / B, nz = z / B;
+    // x, y, z < nc <= 2^20, where the float reciprocal gives exact quotients
+    const int nx = fdivi(x, P.inv_leaf_block), ny = fdivi(y, P.inv_leaf_block),
+              nz = fdivi(z, P.inv_leaf_block);
     const int leaf = P.leaf_map[(nx * side + ny) * side + nz];
     if (leaf < 0) return -1;
     return (int64_t)leaf * B * B * B + ((x - nx * B) * B + (y - ny * B)) * B + (z - nz * B);

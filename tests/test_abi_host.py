@@ -108,3 +108,21 @@ def test_launch_shape_validation(psd):
         with pytest.raises(psd.PsdError) as e:
             psd.uniform_workspace_size((8, 8, 8), 16, tuning=bad)
         assert e.value.code == psd.PSD_ERR_ARG
+
+
+def test_float_reciprocal_quotient_is_exact():
+    """The kernels divide cell and column indices n < 2^20 by small integers d
+    (an octree leaf side up to 4096, a tile width) as trunc((n + 1/2) * (1/d))
+    in FP32, with 1/d rounded to float: the rounding error stays below the
+    1/(2d) that separates (n + 1/2)/d from an integer, so the quotient is
+    exact.  Checked here with IEEE FP32 arithmetic for every n."""
+    import numpy as np
+    n = np.arange(1 << 20, dtype=np.int64)
+    nf = n.astype(np.float32) + np.float32(0.5)
+    rng = np.random.default_rng(7)
+    ds = sorted(set(range(1, 65)) | {1 << k for k in range(13)} | {4095, 4093, 3001, 2047}
+                | set(int(d) for d in rng.integers(65, 4097, 60)))
+    for d in ds:
+        inv = np.float32(1.0 / d)
+        q = (nf * inv).astype(np.int64)
+        assert np.array_equal(q, n // d), d

@@ -42,6 +42,8 @@ CASES = [
     ("complete", lambda: zeldovich_positions(8, 0.3, seed=31), 2, 2, 4, 0),
     ("zel32_adaptive", lambda: zeldovich_positions(32, 1.5, seed=61), 4, 3, 8, 3000),
     ("clumps64", lambda: apply_clumps(zeldovich_positions(64, 2.0, seed=62), seed=63), 4, 4, 8, 20000),
+    # leaves of 3^3 cells (a block that is not a power of two) at levels 2 and 3
+    ("zel32_block3", lambda: zeldovich_positions(32, 1.5, seed=64), 3, 3, 8, 3000),
 ]
 
 
