@@ -88,14 +88,26 @@ __device__ __forceinline__ int wrap_add(int base, int off, int n)
 }
 
 // Output index of grid cell (x,y,z) (wrapped into [0,nc)), or -1 when the
-// cell belongs to no leaf of this octree level.
+// cell belongs to no leaf of this octree level.  RCP: the node quotients by
+// the float reciprocal of B (x, y, z < nc <= 2^20, where it is exact), which
+// is cheaper than integer division but costs the large-buffer instances
+// registers they do not have.
+template <bool RCP = false>
 __device__ __forceinline__ int64_t out_index(const BoxDesc& P, int x, int y, int z)
 {
     if (!P.leaf_map) return ((int64_t)x * P.nc[1] + y) * P.nc[2] + z;
     const int B = P.leaf_block, side = P.leaf_side;
-    // x, y, z < nc <= 2^20, where the float reciprocal gives exact quotients
-    const int nx = fdivi(x, P.inv_leaf_block), ny = fdivi(y, P.inv_leaf_block),
-              nz = fdivi(z, P.inv_leaf_block);
+    int nx, ny, nz;
+    if constexpr (RCP) {
+        const float inv = 1.0f / (float)B;  // loop-invariant: hoisted by the compiler
+        nx = fdivi(x, inv);
+        ny = fdivi(y, inv);
+        nz = fdivi(z, inv);
+    } else {
+        nx = x / B;
+        ny = y / B;
+        nz = z / B;
+    }
     const int leaf = P.leaf_map[(nx * side + ny) * side + nz];
     if (leaf < 0) return -1;
     return (int64_t)leaf * B * B * B + ((x - nx * B) * B + (y - ny * B)) * B + (z - nz * B);
@@ -713,8 +725,8 @@ __global__ __launch_bounds__(kWave, (CAP <= 1408 ? 3 : 2)) void queue_kernel(Que
                                 // differences of values up to 1 carry ~1e-16 noise: drop it
                                 if (V > 4e-15) {
                                     const int w = wrap_add(gw, l, nw);
-                                    const int64_t gi = out_index(P, k2 == 0 ? w : gx, k2 == 1 ? w : gy,
-                                                                 k2 == 2 ? w : gz);
+                                    const int64_t gi = out_index<(CAP <= 960)>(
+                                        P, k2 == 0 ? w : gx, k2 == 1 ? w : gy, k2 == 2 ? w : gz);
                                     if (gi >= 0) {
                                         ++n_nz;
                                         const double mass = P.m * V;

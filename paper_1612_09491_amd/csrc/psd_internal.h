@@ -60,7 +60,6 @@ struct BoxDesc {
     const int* level_has_leaf; // octree level: nothing to do when 0
     int leaf_block;
     int leaf_side;
-    float inv_leaf_block;      // 1 / leaf_block rounded to float (cell -> node by fdivi)
     int skip_small;            // leave bboxes of 2..8 cells within 2x2x2 to the surrogate
     // per 64-tet chunk, the tets left to this deposit (bit = lane), or null
     const unsigned long long* exact_mask;

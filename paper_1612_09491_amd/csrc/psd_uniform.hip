@@ -446,7 +446,6 @@ BoxDesc box_from_uniform(const UniformArgs& P)
     b.level_has_leaf = P.level_has_leaf;
     b.leaf_block = P.leaf_block;
     b.leaf_side = P.leaf_side;
-    b.inv_leaf_block = P.leaf_block > 0 ? (float)(1.0 / P.leaf_block) : 0.0f;
     b.skip_small = P.surrogate != nullptr;
     return b;
 }
