@@ -716,22 +716,50 @@ __global__ __launch_bounds__(kWave, (CAP <= 1408 ? 3 : 2)) void queue_kernel(Que
                             const int gw = k2 == 0 ? gx : (k2 == 1 ? gy : gz);
                             const int nw = k2 == 0 ? P.nc[0] : (k2 == 1 ? P.nc[1] : P.nc[2]);
                             n_pair += t.tl;
-                            for (int l = 0; l < t.tl; ++l) {
-                                const double d11 = D11[l];
-                                const double d01 = has_a ? D01[l] : 0.0;
-                                const double d10 = has_b ? D10[l] : 0.0;
-                                const double d00 = (has_a && has_b) ? D00[l] : 0.0;
-                                const double V = (d11 - d01) - (d10 - d00);
-                                // differences of values up to 1 carry ~1e-16 noise: drop it
-                                if (V > 4e-15) {
-                                    const int w = wrap_add(gw, l, nw);
-                                    const int64_t gi = out_index<(CAP <= 960)>(
-                                        P, k2 == 0 ? w : gx, k2 == 1 ? w : gy, k2 == 2 ? w : gz);
-                                    if (gi >= 0) {
+                            // the cell's mass: (d11 - d01) - (d10 - d00); differences of
+                            // values up to 1 carry ~1e-16 noise, which is dropped
+                            if (!P.leaf_map) {
+                                // plain grid: the element of level 0, then one stride of
+                                // the walk axis per level, nw strides back at the wrap
+                                const int64_t step = k2 == 0 ? (int64_t)P.nc[1] * P.nc[2]
+                                                             : (k2 == 1 ? (int64_t)P.nc[2] : 1);
+                                OutT* po = out + ((int64_t)gx * P.nc[1] + gy) * P.nc[2] + gz;
+                                int w = gw;
+                                for (int l = 0; l < t.tl; ++l) {
+                                    const double d11 = D11[l];
+                                    const double d01 = has_a ? D01[l] : 0.0;
+                                    const double d10 = has_b ? D10[l] : 0.0;
+                                    const double d00 = (has_a && has_b) ? D00[l] : 0.0;
+                                    const double V = (d11 - d01) - (d10 - d00);
+                                    if (V > 4e-15) {
                                         ++n_nz;
                                         const double mass = P.m * V;
-                                        atomicAdd(out + gi, (OutT)(mass * P.out_scale));
+                                        atomicAdd(po, (OutT)(mass * P.out_scale));
                                         macc += mass;
+                                    }
+                                    po += step;
+                                    if (++w == nw) {
+                                        w = 0;
+                                        po -= step * nw;
+                                    }
+                                }
+                            } else {
+                                for (int l = 0; l < t.tl; ++l) {
+                                    const double d11 = D11[l];
+                                    const double d01 = has_a ? D01[l] : 0.0;
+                                    const double d10 = has_b ? D10[l] : 0.0;
+                                    const double d00 = (has_a && has_b) ? D00[l] : 0.0;
+                                    const double V = (d11 - d01) - (d10 - d00);
+                                    if (V > 4e-15) {
+                                        const int w = wrap_add(gw, l, nw);
+                                        const int64_t gi = out_index<(CAP <= 960)>(
+                                            P, k2 == 0 ? w : gx, k2 == 1 ? w : gy, k2 == 2 ? w : gz);
+                                        if (gi >= 0) {
+                                            ++n_nz;
+                                            const double mass = P.m * V;
+                                            atomicAdd(out + gi, (OutT)(mass * P.out_scale));
+                                            macc += mass;
+                                        }
                                     }
                                 }
                             }
