@@ -181,7 +181,8 @@ psd_status psd_autotune_batched(const psd_box* boxes, int32_t n_boxes, const psd
 
 typedef struct {
     int32_t block_cells; /* B: cells per leaf side (the paper's tests use 128
-                            and 64; 16 here), >= 1                            */
+                            and 64; 16 here), 1..1024 (cells within a leaf
+                            are indexed in 32 bits)                           */
     int32_t max_level;   /* refinements below the root, 0..7                 */
     int32_t subblock;    /* Lagrangian cubes per subblock side (paper: 8)    */
     int32_t reserved;    /* must be 0                                        */

@@ -90,9 +90,11 @@ size_t uniform_ws_bytes(const psd_particles* p, const psd_options* opt)
     return b;
 }
 
+// Leaves of at most 1024^3 cells: the kernels index cells within a leaf in
+// 32 bits.
 bool octree_params_ok(const psd_octree_params* op)
 {
-    return op && op->block_cells >= 1 && op->block_cells <= 4096 && op->max_level >= 0 &&
+    return op && op->block_cells >= 1 && op->block_cells <= 1024 && op->max_level >= 0 &&
            op->max_level <= 7 && op->subblock >= 1 && op->reserved == 0 && op->threshold >= 0 &&
            ((int64_t)op->block_cells << op->max_level) <= (1 << 20);
 }

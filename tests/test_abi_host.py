@@ -112,7 +112,7 @@ def test_launch_shape_validation(psd):
 
 def test_float_reciprocal_quotient_is_exact():
     """The kernels divide cell and column indices n < 2^20 by small integers d
-    (an octree leaf side up to 4096, a tile width) as trunc((n + 1/2) * (1/d))
+    (an octree leaf side up to 1024, a tile width) as trunc((n + 1/2) * (1/d))
     in FP32, with 1/d rounded to float: the rounding error stays below the
     1/(2d) that separates (n + 1/2)/d from an integer, so the quotient is
     exact.  Checked here with IEEE FP32 arithmetic for every n."""
@@ -126,3 +126,11 @@ def test_float_reciprocal_quotient_is_exact():
         inv = np.float32(1.0 / d)
         q = (nf * inv).astype(np.int64)
         assert np.array_equal(q, n // d), d
+
+
+def test_octree_leaf_side_limit(psd):
+    # cells within a leaf are indexed in 32 bits: leaves of up to 1024^3 cells
+    assert psd.octree_workspace_size((8, 8, 8), block=1024, max_level=0) > 0
+    with pytest.raises(psd.PsdError) as e:
+        psd.octree_workspace_size((8, 8, 8), block=1025, max_level=0)
+    assert e.value.code == psd.PSD_ERR_ARG
