@@ -88,26 +88,12 @@ __device__ __forceinline__ int wrap_add(int base, int off, int n)
 }
 
 // Output index of grid cell (x,y,z) (wrapped into [0,nc)), or -1 when the
-// cell belongs to no leaf of this octree level.  RCP: the node quotients by
-// the float reciprocal of B (x, y, z < nc <= 2^20, where it is exact), which
-// is cheaper than integer division but costs the large-buffer instances
-// registers they do not have.
-template <bool RCP = false>
+// cell belongs to no leaf of this octree level.
 __device__ __forceinline__ int64_t out_index(const BoxDesc& P, int x, int y, int z)
 {
     if (!P.leaf_map) return ((int64_t)x * P.nc[1] + y) * P.nc[2] + z;
     const int B = P.leaf_block, side = P.leaf_side;
-    int nx, ny, nz;
-    if constexpr (RCP) {
-        const float inv = 1.0f / (float)B;  // loop-invariant: hoisted by the compiler
-        nx = fdivi(x, inv);
-        ny = fdivi(y, inv);
-        nz = fdivi(z, inv);
-    } else {
-        nx = x / B;
-        ny = y / B;
-        nz = z / B;
-    }
+    const int nx = x / B, ny = y / B, nz = z / B;
     const int leaf = P.leaf_map[(nx * side + ny) * side + nz];
     if (leaf < 0) return -1;
     return (int64_t)leaf * B * B * B + ((x - nx * B) * B + (y - ny * B)) * B + (z - nz * B);
@@ -743,7 +729,49 @@ __global__ __launch_bounds__(kWave, (CAP <= 1408 ? 3 : 2)) void queue_kernel(Que
                                         po -= step * nw;
                                     }
                                 }
+                            } else if constexpr (CAP <= 960) {
+                                // octree level (the instances for small tets): the node
+                                // and in-leaf offset of level 0, then one cell of the
+                                // walk axis per level; the leaf map is read again where
+                                // the walk enters the next node
+                                const int B = P.leaf_block, side = P.leaf_side;
+                                const int cx = gx / B, cy = gy / B, cz = gz / B;
+                                const int rx = gx - cx * B, ry = gy - cy * B, rz = gz - cz * B;
+                                int off = (rx * B + ry) * B + rz;  // < B^3 <= 2^30
+                                int node = (cx * side + cy) * side + cz;
+                                const int ostep = k2 == 0 ? B * B : (k2 == 1 ? B : 1);
+                                const int nstep = k2 == 0 ? side * side : (k2 == 1 ? side : 1);
+                                int rw = k2 == 0 ? rx : (k2 == 1 ? ry : rz);
+                                int qw = k2 == 0 ? cx : (k2 == 1 ? cy : cz);
+                                int leaf = P.leaf_map[node];
+                                for (int l = 0; l < t.tl; ++l) {
+                                    const double d11 = D11[l];
+                                    const double d01 = has_a ? D01[l] : 0.0;
+                                    const double d10 = has_b ? D10[l] : 0.0;
+                                    const double d00 = (has_a && has_b) ? D00[l] : 0.0;
+                                    const double V = (d11 - d01) - (d10 - d00);
+                                    if (V > 4e-15 && leaf >= 0) {
+                                        ++n_nz;
+                                        const double mass = P.m * V;
+                                        atomicAdd(out + ((int64_t)leaf * B * B * B + off),
+                                                  (OutT)(mass * P.out_scale));
+                                        macc += mass;
+                                    }
+                                    off += ostep;
+                                    if (++rw == B) {
+                                        rw = 0;
+                                        off -= B * ostep;
+                                        node += nstep;
+                                        if (++qw == side) {
+                                            qw = 0;
+                                            node -= side * nstep;
+                                        }
+                                        leaf = P.leaf_map[node];
+                                    }
+                                }
                             } else {
+                                // octree level (large-tet instances, which have no
+                                // registers to spare): each non-zero cell mapped alone
                                 for (int l = 0; l < t.tl; ++l) {
                                     const double d11 = D11[l];
                                     const double d01 = has_a ? D01[l] : 0.0;
@@ -752,8 +780,8 @@ __global__ __launch_bounds__(kWave, (CAP <= 1408 ? 3 : 2)) void queue_kernel(Que
                                     const double V = (d11 - d01) - (d10 - d00);
                                     if (V > 4e-15) {
                                         const int w = wrap_add(gw, l, nw);
-                                        const int64_t gi = out_index<(CAP <= 960)>(
-                                            P, k2 == 0 ? w : gx, k2 == 1 ? w : gy, k2 == 2 ? w : gz);
+                                        const int64_t gi = out_index(P, k2 == 0 ? w : gx,
+                                                                     k2 == 1 ? w : gy, k2 == 2 ? w : gz);
                                         if (gi >= 0) {
                                             ++n_nz;
                                             const double mass = P.m * V;
