@@ -111,8 +111,8 @@ def test_launch_shape_validation(psd):
 
 
 def test_float_reciprocal_quotient_is_exact():
-    """The kernels divide cell and column indices n < 2^20 by small integers d
-    (an octree leaf side up to 1024, a tile width) as trunc((n + 1/2) * (1/d))
+    """The deposit kernel divides column indices n < 2^20 by small integers d
+    (a tile's width in columns) as trunc((n + 1/2) * (1/d))
     in FP32, with 1/d rounded to float: the rounding error stays below the
     1/(2d) that separates (n + 1/2)/d from an integer, so the quotient is
     exact.  Checked here with IEEE FP32 arithmetic for every n."""
