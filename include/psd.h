@@ -17,6 +17,10 @@
  *   - Positions: float32 [np0][np1][np2][3], C order (x index slowest), in a
  *     periodic cube of side `box`; any finite value is accepted and wrapped.
  *     Each cube's corners are unwrapped to the minimum image of corner 000.
+ *     A tetrahedron with a NaN or infinite vertex coordinate cannot be
+ *     placed: the deposits drop it (stats[7] counts it, mass_sum misses its
+ *     mass) unless PSD_CHECK_FINITE asks for the positions to be checked
+ *     first, in which case the call fails with PSD_ERR_NONFINITE.
  *   - Mass per tetrahedron m = total_mass / (6 np0 np1 np2).
  *   - Grids: [nc0][nc1][nc2], C order, cell (a,b,c) covers
  *     [a,a+1) x [b,b+1) x [c,c+1) in units of h_k = box / nc_k.
@@ -43,7 +47,9 @@ typedef enum {
     PSD_ERR_ARG = -1,         /* null pointer, non-positive size, bad value   */
     PSD_ERR_WORKSPACE = -2,   /* workspace smaller than psd_*_workspace_size  */
     PSD_ERR_CAPACITY = -3,    /* octree node array too small (see below)      */
-    PSD_ERR_NONFINITE = -4,   /* reserved                                      */
+    PSD_ERR_NONFINITE = -4,   /* a position is NaN or infinite (only reported
+                                 when checked: PSD_CHECK_FINITE, and always
+                                 by psd_build_octree)                         */
     PSD_ERR_UNSUPPORTED = -5, /* flag combination not supported               */
     PSD_ERR_HIP = -6          /* a HIP runtime call failed (see detail string) */
 } psd_status;
@@ -56,12 +62,26 @@ enum {
     PSD_METHOD_CELL = 1u << 3, /* per-cell exact clip in cell-local FP32
                                   coordinates (Section 6.1 loop cell by cell);
                                   default: cumulative FP64 volumes            */
-    PSD_SURROGATE = 1u << 4    /* tetrahedra whose bbox holds 2..8 cells
+    PSD_SURROGATE = 1u << 4,   /* tetrahedra whose bbox holds 2..8 cells
                                   inside a 2x2x2 block are deposited with the
                                   learned overlap network (psd_options.
                                   surrogate, see the end of this header)
                                   instead of the exact clip; default method
                                   only                                         */
+    PSD_CHECK_FINITE = 1u << 5, /* before any work, scan every position on the
+                                  device and return PSD_ERR_NONFINITE (with
+                                  nothing else enqueued and the outputs
+                                  untouched) if one is NaN or infinite.  The
+                                  call then synchronizes `stream`.            */
+    PSD_WORK_COUNTERS = 1u << 6 /* with stats: stats holds 16 entries and the
+                                  default (cumulative) method runs an
+                                  instrumented kernel that also adds its work
+                                  events into [8] pieces of the first split,
+                                  [9] pieces of the second split (z
+                                  distributions set up), [10] z levels walked
+                                  by those pieces, [11] (column, level) slots
+                                  of the walked tiles; [12..15] reserved.  For
+                                  measurement: the plain kernel is faster.    */
 };
 
 typedef struct {
@@ -93,7 +113,12 @@ typedef struct {
                           [3] non-zero deposits, [4] inverted tets,
                           [5] zero-volume tets, [6] tets deposited by the
                           surrogate (their bbox pairs are not in [1]),
-                          [7] reserved; may be NULL                        */
+                          [7] tets dropped because a vertex coordinate is
+                          NaN or infinite (their mass is deposited nowhere
+                          and is missing from mass_sum); may be NULL.
+                          An octree deposit walks the tetrahedra once per
+                          level that has leaves and counts [0], [4], [7]
+                          on each such walk.                               */
     const psd_tuning* tuning; /* host, may be NULL                           */
     const float* surrogate;   /* DEVICE float[PSD_SURROGATE_PARAMS], the
                                  network for PSD_SURROGATE; else ignored     */
@@ -123,7 +148,8 @@ psd_status psd_uniform_workspace_size(const psd_particles* p, const int32_t nc[3
  *             to the FP64 sum of every mass deposited by this call
  *   opt       host, may be NULL (flags 0)
  *   ws        DEVICE workspace of ws_bytes >= psd_uniform_workspace_size
- * Errors: PSD_ERR_ARG, PSD_ERR_WORKSPACE, PSD_ERR_HIP.  Asynchronous.
+ * Errors: PSD_ERR_ARG, PSD_ERR_WORKSPACE, PSD_ERR_HIP, PSD_ERR_NONFINITE
+ * (PSD_CHECK_FINITE only).  Asynchronous unless PSD_CHECK_FINITE is set.
  */
 psd_status psd_deposit_uniform(const float* pos, const psd_particles* p, const int32_t nc[3],
                                void* out, double* mass_sum, const psd_options* opt, void* ws,
@@ -153,9 +179,9 @@ psd_status psd_batched_workspace_size(const psd_box* boxes, int32_t n_boxes,
  * very different size (the kernel-level load balancing of Section 5).
  *   boxes      host array of n_boxes descriptors (n_boxes >= 1)
  *   mass_sums  DEVICE double[n_boxes] or NULL: per-box FP64 mass sums
- *   flags      PSD_OUT_DENSITY, PSD_ACCUMULATE
- * Errors: PSD_ERR_ARG, PSD_ERR_WORKSPACE, PSD_ERR_UNSUPPORTED, PSD_ERR_HIP.
- * Asynchronous.
+ *   flags      PSD_OUT_DENSITY, PSD_ACCUMULATE, PSD_CHECK_FINITE (every box)
+ * Errors: PSD_ERR_ARG, PSD_ERR_WORKSPACE, PSD_ERR_UNSUPPORTED, PSD_ERR_HIP,
+ * PSD_ERR_NONFINITE.  Asynchronous unless PSD_CHECK_FINITE is set.
  */
 psd_status psd_deposit_batched(const psd_box* boxes, int32_t n_boxes, double* mass_sums,
                                const psd_options* opt, void* ws, size_t ws_bytes, void* stream);
@@ -215,7 +241,8 @@ psd_status psd_octree_workspace_size(const psd_particles* p, const psd_octree_pa
  *             children of a node contiguous -- leaves numbered in node order
  *   n_nodes, n_leaves  host out
  * Returns PSD_ERR_CAPACITY (with *n_nodes, *n_leaves set) when capacity is
- * too small.  Synchronizes `stream`.
+ * too small, PSD_ERR_NONFINITE (nodes untouched) when a position is NaN or
+ * infinite (the positions are always checked).  Synchronizes `stream`.
  */
 psd_status psd_build_octree(const float* pos, const psd_particles* p, const psd_octree_params* op,
                             psd_octree_node* nodes, int64_t capacity, int64_t* n_nodes,
@@ -231,14 +258,75 @@ psd_status psd_build_octree(const float* pos, const psd_particles* p, const psd_
  *   out       DEVICE float [n_leaves][B][B][B], zeroed first unless
  *             PSD_ACCUMULATE
  *   mass_sum  DEVICE double[1] or NULL (FP64 sum of deposited mass)
- *   flags     PSD_OUT_DENSITY, PSD_ACCUMULATE
- * Errors: PSD_ERR_ARG, PSD_ERR_WORKSPACE, PSD_ERR_UNSUPPORTED, PSD_ERR_HIP.
- * Asynchronous.
+ *   flags     PSD_OUT_DENSITY, PSD_ACCUMULATE, PSD_CHECK_FINITE
+ * Errors: PSD_ERR_ARG, PSD_ERR_WORKSPACE, PSD_ERR_UNSUPPORTED, PSD_ERR_HIP,
+ * PSD_ERR_NONFINITE.  Asynchronous unless PSD_CHECK_FINITE is set.
  */
 psd_status psd_deposit_octree(const float* pos, const psd_particles* p, const psd_octree_params* op,
                               const psd_octree_node* nodes, int64_t n_nodes, int64_t n_leaves,
                               float* out, double* mass_sum, const psd_options* opt, void* ws,
                               size_t ws_bytes, void* stream);
+
+/*
+ * Coarse representations of the internal nodes (Section 8, future work: the
+ * leaves' deposit plus coarser levels for multi-resolution rendering).  For
+ * every node, the B^3 cells of its region at its own resolution, box / (B
+ * 2^level): a leaf's block is copied from `leaves`; an internal node's cell
+ * is the sum (PSD_OUT_DENSITY: the average) of the 2x2x2 cells of its
+ * children that it covers -- exact, since |T cap C| is additive over a
+ * partition of C -- accumulated in FP64 in the fixed order dx, dy, dz (x
+ * outermost) and rounded once to FP32 per level.  Levels are filled
+ * bottom-up, so node values do not depend on the launch.
+ *   nodes     DEVICE node array from psd_build_octree (n_nodes entries)
+ *   leaves    DEVICE float [n_leaves][B][B][B] from psd_deposit_octree
+ *             (masses, or densities with PSD_OUT_DENSITY)
+ *   out       DEVICE float [n_nodes][B][B][B], node order; must not overlap
+ *             `leaves`
+ *   block     B, the tree's cells per leaf side; even unless the tree is a
+ *             single leaf
+ *   max_level the tree's max_level
+ *   flags     0 (masses) or PSD_OUT_DENSITY
+ * Nodes that are malformed (a child range outside the array, two children in
+ * one octant, a leaf id >= n_leaves) are skipped and their blocks left as
+ * they were.  Errors: PSD_ERR_ARG, PSD_ERR_UNSUPPORTED (odd block with
+ * internal nodes), PSD_ERR_HIP.  Asynchronous.
+ */
+psd_status psd_octree_coarsen(const psd_octree_node* nodes, int64_t n_nodes, int64_t n_leaves,
+                              int32_t block, int32_t max_level, const float* leaves, float* out,
+                              uint32_t flags, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Snapshot ingest (Section 3)                                                */
+/* ------------------------------------------------------------------------ */
+
+/* Workspace bytes (host out) of psd_reorder_by_id with a check: one bit per
+ * Lagrangian slot, rounded up to 32-bit words. */
+psd_status psd_reorder_workspace_size(const int32_t np[3], size_t* bytes);
+
+/*
+ * Places snapshot records on the Lagrangian grid.  A snapshot holds tracers
+ * in an arbitrary order, each with a unique ID that gives its Lagrangian
+ * position (Section 3; once sorted by ID the IDs are dropped).  Record r goes
+ * to slot ids[r] - id_base, slot (i * np1 + j) * np2 + k holding particle
+ * (i, j, k): pos_out[slot][0..2] = pos_in[r][0..2], bit for bit.
+ *   ids       DEVICE int64 [n]
+ *   pos_in    DEVICE float [n][3]
+ *   n         records, >= 0 (need not equal the slot count)
+ *   np        host, the Lagrangian grid size (each >= 1)
+ *   pos_out   DEVICE float [np0][np1][np2][3]; must not overlap pos_in; slots
+ *             that no record names keep their contents; when several records
+ *             name one slot, one of them (unspecified) is stored
+ *   check     DEVICE int64[3] or NULL: set to [0] records whose id is outside
+ *             [id_base, id_base + np0 np1 np2) (skipped), [1] records naming a
+ *             slot another record already named, [2] slots no record names.
+ *             A valid snapshot (a permutation) gives 0, 0, 0.
+ *   ws        DEVICE workspace of psd_reorder_workspace_size bytes when check
+ *             is not NULL (may be NULL otherwise)
+ * Errors: PSD_ERR_ARG, PSD_ERR_WORKSPACE, PSD_ERR_HIP.  Asynchronous.
+ */
+psd_status psd_reorder_by_id(const int64_t* ids, const float* pos_in, int64_t n, int64_t id_base,
+                             const int32_t np[3], float* pos_out, int64_t* check, void* ws,
+                             size_t ws_bytes, void* stream);
 
 /* Human-readable name of a status code (static string). */
 const char* psd_status_string(psd_status s);

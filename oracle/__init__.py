@@ -20,3 +20,4 @@ from .oracle import (  # noqa: F401
     TRIVIAL,
     PAPER,
 )
+from .ingest import reorder_by_id, coarse_levels  # noqa: F401

@@ -30,11 +30,15 @@ PSD_ACCUMULATE = 1 << 1
 PSD_PREC_FP64 = 1 << 2
 PSD_METHOD_CELL = 1 << 3
 PSD_SURROGATE = 1 << 4
+PSD_CHECK_FINITE = 1 << 5
+PSD_WORK_COUNTERS = 1 << 6
 
 PSD_SURROGATE_PARAMS = 9672
 
 STAT_NAMES = ("tets", "pairs", "clips_or_columns", "nonzero", "inverted", "degenerate",
-              "surrogate_tets")
+              "surrogate_tets", "dropped_nonfinite")
+# stats[8..11] with PSD_WORK_COUNTERS (the stats tensor then has 16 entries)
+WORK_STAT_NAMES = ("xpieces", "pieces", "levels", "column_levels")
 
 
 class PsdError(RuntimeError):
@@ -109,6 +113,32 @@ def _grid3(nc) -> tuple[int, int, int]:
     return t
 
 
+def _check_aux(mass_sum, n_sums: int, stats, flags: int = 0) -> None:
+    """The optional device outputs every deposit takes: FP64 mass sums (n_sums of them)
+    and the int64 counters (8 of them, 16 with PSD_WORK_COUNTERS); the kernels add into
+    them with 8-byte atomics."""
+    if mass_sum is not None and (not isinstance(mass_sum, torch.Tensor) or
+                                 mass_sum.dtype != torch.float64 or not mass_sum.is_cuda or
+                                 not mass_sum.is_contiguous() or mass_sum.numel() < n_sums):
+        raise ValueError(f"mass_sum must be a contiguous CUDA float64 tensor with {n_sums} "
+                         f"entr{'y' if n_sums == 1 else 'ies'}")
+    n_stats = 16 if flags & PSD_WORK_COUNTERS else 8
+    if stats is not None and (not isinstance(stats, torch.Tensor) or stats.dtype != torch.int64 or
+                              not stats.is_cuda or not stats.is_contiguous() or
+                              stats.numel() < n_stats):
+        raise ValueError(f"stats must be a contiguous CUDA int64 tensor with {n_stats} entries")
+
+
+def _workspace(workspace, nbytes: int, device) -> torch.Tensor:
+    """The caller's workspace (a CUDA tensor of at least nbytes bytes) or a new one."""
+    if workspace is None:
+        return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+    if not isinstance(workspace, torch.Tensor) or not workspace.is_cuda or \
+            not workspace.is_contiguous() or workspace.numel() * workspace.element_size() < nbytes:
+        raise ValueError(f"workspace must be a contiguous CUDA tensor of at least {nbytes} bytes")
+    return workspace
+
+
 def _stream_handle(stream) -> int:
     s = torch.cuda.current_stream() if stream is None else stream
     return int(s.cuda_stream)
@@ -162,17 +192,14 @@ def deposit_uniform(pos: torch.Tensor, nc, box: float = 1.0, mass: float = 1.0, 
     elif out.dtype != dtype or tuple(out.shape) != g or not out.is_contiguous() or not out.is_cuda:
         raise ValueError(f"out must be a contiguous CUDA {dtype} tensor of shape {g}")
     nbytes = uniform_workspace_size(tuple(pos.shape[:3]), g, flags, box, mass, tuning)
-    if workspace is None:
-        workspace = torch.empty(nbytes, dtype=torch.uint8, device=pos.device)
-    if mass_sum is not None and (mass_sum.dtype != torch.float64 or not mass_sum.is_cuda):
-        raise ValueError("mass_sum must be a CUDA float64 tensor")
-    if stats is not None and (stats.dtype != torch.int64 or stats.numel() < 8 or not stats.is_cuda):
-        raise ValueError("stats must be a CUDA int64 tensor with 8 entries")
+    workspace = _workspace(workspace, nbytes, pos.device)
+    _check_aux(mass_sum, 1, stats, flags)
     o = _options(flags, stats, tuning, surrogate)
     ncs = (C.c_int32 * 3)(*g)
     _check(lib().psd_deposit_uniform(pos.data_ptr(), C.byref(p), ncs, out.data_ptr(),
                                      mass_sum.data_ptr() if mass_sum is not None else None,
-                                     C.byref(o), workspace.data_ptr(), workspace.numel(),
+                                     C.byref(o), workspace.data_ptr(),
+                                     workspace.numel() * workspace.element_size(),
                                      _stream_handle(stream)),
            "psd_deposit_uniform")
     return out
@@ -257,11 +284,11 @@ def build_octree(pos: torch.Tensor, block: int = 16, max_level: int = 4, subbloc
     cap = max_nodes(max_level) if capacity is None else int(capacity)
     nodes = torch.empty(max(cap, 1) * NODE_BYTES, dtype=torch.uint8, device=pos.device)
     nbytes = octree_workspace_size(tuple(pos.shape[:3]), block, max_level, subblock, threshold, box)
-    if workspace is None:
-        workspace = torch.empty(nbytes, dtype=torch.uint8, device=pos.device)
+    workspace = _workspace(workspace, nbytes, pos.device)
     nn, nl = C.c_int64(0), C.c_int64(0)
     code = L.psd_build_octree(pos.data_ptr(), C.byref(p), C.byref(op), nodes.data_ptr(), cap,
-                              C.byref(nn), C.byref(nl), workspace.data_ptr(), workspace.numel(),
+                              C.byref(nn), C.byref(nl), workspace.data_ptr(),
+                              workspace.numel() * workspace.element_size(),
                               _stream_handle(stream))
     if code == PSD_ERR_CAPACITY:
         err = PsdError(code, "psd_build_octree", f"needs {nn.value} nodes")
@@ -284,17 +311,21 @@ def deposit_octree(pos: torch.Tensor, tree: Octree, box: float = 1.0, mass: floa
     shape = (tree.n_leaves, B, B, B)
     if out is None:
         out = torch.empty(shape, dtype=torch.float32, device=pos.device)
-    elif out.dtype != torch.float32 or tuple(out.shape) != shape or not out.is_contiguous():
-        raise ValueError(f"out must be a contiguous float32 tensor of shape {shape}")
+    elif (out.dtype != torch.float32 or tuple(out.shape) != shape or not out.is_contiguous() or
+          not out.is_cuda):
+        raise ValueError(f"out must be a contiguous CUDA float32 tensor of shape {shape}")
+    if not tree.nodes.is_cuda:
+        raise ValueError("the octree's node array must be on the GPU")
     nbytes = octree_workspace_size(tuple(pos.shape[:3]), tree.block, tree.max_level, tree.subblock,
                                    tree.threshold, box)
-    if workspace is None:
-        workspace = torch.empty(nbytes, dtype=torch.uint8, device=pos.device)
+    workspace = _workspace(workspace, nbytes, pos.device)
+    _check_aux(mass_sum, 1, stats, flags)
     o = _options(flags, stats, tuning)
     _check(L.psd_deposit_octree(pos.data_ptr(), C.byref(p), C.byref(op), tree.nodes.data_ptr(),
                                 tree.n_nodes, tree.n_leaves, out.data_ptr(),
                                 mass_sum.data_ptr() if mass_sum is not None else None,
-                                C.byref(o), workspace.data_ptr(), workspace.numel(),
+                                C.byref(o), workspace.data_ptr(),
+                                workspace.numel() * workspace.element_size(),
                                 _stream_handle(stream)),
            "psd_deposit_octree")
     return out
@@ -334,8 +365,9 @@ def _box_array(boxes, box: float, mass: float, flags: int):
         p = _particles(pos, box, mass)
         if out is None:
             out = torch.empty(nc, dtype=torch.float32, device=pos.device)
-        elif out.dtype != torch.float32 or tuple(out.shape) != nc or not out.is_contiguous():
-            raise ValueError(f"box {i}: out must be a contiguous float32 tensor of shape {nc}")
+        elif (out.dtype != torch.float32 or tuple(out.shape) != nc or not out.is_contiguous() or
+              not out.is_cuda):
+            raise ValueError(f"box {i}: out must be a contiguous CUDA float32 tensor of shape {nc}")
         arr[i].pos = pos.data_ptr()
         arr[i].p = p
         for a in range(3):
@@ -372,12 +404,11 @@ def deposit_batched(boxes, box: float = 1.0, mass: float = 1.0, flags: int = 0,
     _check(L.psd_batched_workspace_size(arr, len(arr), C.byref(o), C.byref(nbytes)),
            "psd_batched_workspace_size")
     dev = outs[0].device
-    if workspace is None:
-        workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=dev)
-    if mass_sums is not None and (mass_sums.dtype != torch.float64 or mass_sums.numel() < len(arr)):
-        raise ValueError("mass_sums must be float64 with one entry per box")
+    workspace = _workspace(workspace, int(nbytes.value), dev)
+    _check_aux(mass_sums, len(arr), stats, flags)
     _check(L.psd_deposit_batched(arr, len(arr), mass_sums.data_ptr() if mass_sums is not None else None,
-                                 C.byref(o), workspace.data_ptr(), workspace.numel(),
+                                 C.byref(o), workspace.data_ptr(),
+                                 workspace.numel() * workspace.element_size(),
                                  _stream_handle(stream)),
            "psd_deposit_batched")
     return outs
@@ -596,3 +627,94 @@ def train_surrogate(params: torch.Tensor, feat: torch.Tensor, frac: torch.Tensor
         rate *= decay
     state["losses"] = losses
     return state
+
+
+# ---------------------------------------------------------------------------
+# Snapshot ingest and coarse octree levels
+# ---------------------------------------------------------------------------
+
+def _bind_extra(L):
+    if getattr(L, "_extra_bound", False):
+        return
+    L.psd_reorder_workspace_size.restype = C.c_int
+    L.psd_reorder_workspace_size.argtypes = [C.POINTER(C.c_int32), C.POINTER(C.c_size_t)]
+    L.psd_reorder_by_id.restype = C.c_int
+    L.psd_reorder_by_id.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
+                                    C.POINTER(C.c_int32), C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_size_t, C.c_void_p]
+    L.psd_octree_coarsen.restype = C.c_int
+    L.psd_octree_coarsen.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int32, C.c_int32,
+                                     C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p]
+    L._extra_bound = True
+
+
+def reorder_workspace_size(np_) -> int:
+    L = lib()
+    _bind_extra(L)
+    g = (C.c_int32 * 3)(*_grid3(np_))
+    nbytes = C.c_size_t(0)
+    _check(L.psd_reorder_workspace_size(g, C.byref(nbytes)), "psd_reorder_workspace_size")
+    return int(nbytes.value)
+
+
+def reorder_by_id(ids: torch.Tensor, pos_in: torch.Tensor, np_, id_base: int = 0,
+                  out: torch.Tensor | None = None, check: torch.Tensor | None = None,
+                  workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Snapshot records (ids [n] int64, pos_in [n, 3] float32) placed on the Lagrangian grid
+    [np0, np1, np2, 3]: slot ids[r] - id_base gets record r.  ``check`` (int64[3], optional)
+    receives (ids out of range, duplicate slots, slots never named)."""
+    L = lib()
+    _bind_extra(L)
+    g = _grid3(np_)
+    if (not ids.is_cuda or ids.dtype != torch.int64 or ids.dim() != 1 or
+            not ids.is_contiguous()):
+        raise ValueError("ids must be a contiguous CUDA int64 tensor [n]")
+    n = int(ids.numel())
+    if (not pos_in.is_cuda or pos_in.dtype != torch.float32 or tuple(pos_in.shape) != (n, 3) or
+            not pos_in.is_contiguous()):
+        raise ValueError("pos_in must be a contiguous CUDA float32 tensor [n, 3]")
+    shape = g + (3,)
+    if out is None:
+        out = torch.zeros(shape, dtype=torch.float32, device=pos_in.device)
+    elif (out.dtype != torch.float32 or tuple(out.shape) != shape or not out.is_contiguous() or
+          not out.is_cuda):
+        raise ValueError(f"out must be a contiguous CUDA float32 tensor of shape {shape}")
+    if check is not None:
+        if (check.dtype != torch.int64 or not check.is_cuda or check.numel() < 3 or
+                not check.is_contiguous()):
+            raise ValueError("check must be a contiguous CUDA int64 tensor with 3 entries")
+        workspace = _workspace(workspace, reorder_workspace_size(g), pos_in.device)
+    npc = (C.c_int32 * 3)(*g)
+    _check(L.psd_reorder_by_id(ids.data_ptr() if n else None, pos_in.data_ptr() if n else None, n,
+                               int(id_base), npc, out.data_ptr(),
+                               check.data_ptr() if check is not None else None,
+                               workspace.data_ptr() if workspace is not None else None,
+                               workspace.numel() * workspace.element_size()
+                               if workspace is not None else 0,
+                               _stream_handle(stream)),
+           "psd_reorder_by_id")
+    return out
+
+
+def octree_coarsen(tree: "Octree", leaves: torch.Tensor, density: bool = False,
+                   out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Every node's B^3 block [n_nodes, B, B, B] (node order): leaves copied, internal nodes
+    as 2x2x2 sums of their children's cells (averages when ``density``)."""
+    L = lib()
+    _bind_extra(L)
+    B = tree.block
+    lshape = (tree.n_leaves, B, B, B)
+    if (leaves.dtype != torch.float32 or tuple(leaves.shape) != lshape or
+            not leaves.is_contiguous() or not leaves.is_cuda):
+        raise ValueError(f"leaves must be a contiguous CUDA float32 tensor of shape {lshape}")
+    shape = (tree.n_nodes, B, B, B)
+    if out is None:
+        out = torch.zeros(shape, dtype=torch.float32, device=leaves.device)
+    elif (out.dtype != torch.float32 or tuple(out.shape) != shape or not out.is_contiguous() or
+          not out.is_cuda):
+        raise ValueError(f"out must be a contiguous CUDA float32 tensor of shape {shape}")
+    _check(L.psd_octree_coarsen(tree.nodes.data_ptr(), tree.n_nodes, tree.n_leaves, B,
+                                tree.max_level, leaves.data_ptr(), out.data_ptr(),
+                                PSD_OUT_DENSITY if density else 0, _stream_handle(stream)),
+           "psd_octree_coarsen")
+    return out

@@ -60,6 +60,7 @@ psd::Tuning tuning_from(const psd_options* opt)
         if (u->waves_per_cu > 0) t.waves_per_cu = u->waves_per_cu;
         t.ordered = u->ordered ? 1 : 0;
     }
+    if (opt && (opt->flags & PSD_WORK_COUNTERS) && opt->stats) t.work_counters = 1;
     return t;
 }
 
@@ -117,10 +118,39 @@ psd::OctreeArgs octree_args(const float* pos, const psd_particles* p, const psd_
     A.threshold = op->threshold;
     return A;
 }
-constexpr uint32_t kUniformFlags =
-    PSD_OUT_DENSITY | PSD_ACCUMULATE | PSD_PREC_FP64 | PSD_METHOD_CELL | PSD_SURROGATE;
+constexpr uint32_t kUniformFlags = PSD_OUT_DENSITY | PSD_ACCUMULATE | PSD_PREC_FP64 |
+                                   PSD_METHOD_CELL | PSD_SURROGATE | PSD_CHECK_FINITE |
+                                   PSD_WORK_COUNTERS;
+
+// PSD_ERR_NONFINITE when one of the n particles' coordinates is NaN or
+// infinite; the device word `scratch` (inside the caller's workspace) holds
+// the count.  Synchronizes the stream.
+psd_status check_positions(const float* pos, int64_t n_particles, void* scratch,
+                           hipStream_t stream, const char* where)
+{
+    unsigned long long bad = 0;
+    const hipError_t e = psd::count_nonfinite(pos, 3 * n_particles,
+                                              reinterpret_cast<unsigned long long*>(scratch),
+                                              stream, bad);
+    if (e != hipSuccess) return fail_hip(e, where);
+    if (bad) {
+        char msg[128];
+        snprintf(msg, sizeof(msg), "%s: %llu position coordinates are NaN or infinite", where, bad);
+        return fail(PSD_ERR_NONFINITE, msg);
+    }
+    return PSD_OK;
+}
+
+int64_t particle_count(const psd_particles* p)
+{
+    return (int64_t)p->np[0] * p->np[1] * p->np[2];
+}
 
 }  // namespace
+
+namespace psd {
+psd_status set_error(psd_status s, const char* detail) { return fail(s, detail); }
+}  // namespace psd
 
 extern "C" {
 
@@ -172,6 +202,12 @@ psd_status psd_deposit_uniform(const float* pos, const psd_particles* p, const i
             return fail(PSD_ERR_UNSUPPORTED, "PSD_SURROGATE needs the default (cumulative) method");
         if (!opt->surrogate) return fail(PSD_ERR_ARG, "PSD_SURROGATE without parameters");
     }
+    if (flags & PSD_CHECK_FINITE) {
+        // the queue's work counter (offset 0) is free until the deposit starts
+        const psd_status s = check_positions(pos, particle_count(p), ws,
+                                             reinterpret_cast<hipStream_t>(stream), "deposit_uniform");
+        if (s != PSD_OK) return s;
+    }
 
     psd::UniformArgs A;
     memset(&A, 0, sizeof(A));
@@ -208,7 +244,8 @@ static bool boxes_ok(const psd_box* boxes, int32_t n)
     return true;
 }
 
-static const uint32_t kBatchedFlags = PSD_OUT_DENSITY | PSD_ACCUMULATE;
+static const uint32_t kBatchedFlags =
+    PSD_OUT_DENSITY | PSD_ACCUMULATE | PSD_CHECK_FINITE | PSD_WORK_COUNTERS;
 
 psd_status psd_batched_workspace_size(const psd_box* boxes, int32_t n_boxes,
                                       const psd_options* opt, size_t* bytes)
@@ -231,6 +268,13 @@ psd_status psd_deposit_batched(const psd_box* boxes, int32_t n_boxes, double* ma
     const psd::Tuning t = tuning_from(opt);
     if (!ws || ws_bytes < psd::batched_ws_bytes(boxes, n_boxes, t.ordered != 0))
         return fail(PSD_ERR_WORKSPACE, "workspace too small");
+    if (flags & PSD_CHECK_FINITE)
+        for (int32_t b = 0; b < n_boxes; ++b) {
+            const psd_status s = check_positions(boxes[b].pos, particle_count(&boxes[b].p), ws,
+                                                 reinterpret_cast<hipStream_t>(stream),
+                                                 "deposit_batched");
+            if (s != PSD_OK) return s;
+        }
     hipError_t e = psd::launch_batched(boxes, n_boxes, mass_sums, (flags & PSD_OUT_DENSITY) != 0,
                                        (flags & PSD_ACCUMULATE) != 0, t, ws, ws_bytes,
                                        opt ? reinterpret_cast<unsigned long long*>(opt->stats) : nullptr,
@@ -284,6 +328,13 @@ psd_status psd_build_octree(const float* pos, const psd_particles* p, const psd_
     const psd::OctreeArgs A = octree_args(pos, p, op);
     if (!ws || ws_bytes < psd::octree_workspace_layout(A).bytes)
         return fail(PSD_ERR_WORKSPACE, "workspace too small");
+    {
+        // a NaN would turn the subblock boxes, and so the counts, into garbage
+        const psd_status s = check_positions(
+            pos, particle_count(p), static_cast<char*>(ws) + psd::octree_workspace_layout(A).counts,
+            reinterpret_cast<hipStream_t>(stream), "build_octree");
+        if (s != PSD_OK) return s;
+    }
     int64_t counts[2] = {0, 0};
     hipError_t e = psd::launch_build_octree(A, ws, reinterpret_cast<psd::OctNode*>(nodes), capacity,
                                             counts, reinterpret_cast<hipStream_t>(stream));
@@ -306,12 +357,19 @@ psd_status psd_deposit_octree(const float* pos, const psd_particles* p, const ps
         n_nodes > psd::octree_max_nodes(op->max_level))
         return fail(PSD_ERR_ARG, "bad node or leaf count");
     const uint32_t flags = opt ? opt->flags : 0u;
-    if (flags & ~(uint32_t)(PSD_OUT_DENSITY | PSD_ACCUMULATE))
-        return fail(PSD_ERR_UNSUPPORTED, "octree deposit supports PSD_OUT_DENSITY and PSD_ACCUMULATE");
+    if (flags & ~(uint32_t)(PSD_OUT_DENSITY | PSD_ACCUMULATE | PSD_CHECK_FINITE | PSD_WORK_COUNTERS))
+        return fail(PSD_ERR_UNSUPPORTED, "octree deposit supports PSD_OUT_DENSITY, PSD_ACCUMULATE, "
+                                         "PSD_CHECK_FINITE and PSD_WORK_COUNTERS");
     if (!tuning_ok(opt)) return fail(PSD_ERR_ARG, "bad tuning");
     const psd::OctreeArgs A = octree_args(pos, p, op);
     if (!ws || ws_bytes < psd::octree_workspace_layout(A).bytes + psd::octree_queue_bytes(A))
         return fail(PSD_ERR_WORKSPACE, "workspace too small");
+    if (flags & PSD_CHECK_FINITE) {
+        const psd_status s = check_positions(
+            pos, particle_count(p), static_cast<char*>(ws) + psd::octree_workspace_layout(A).counts,
+            reinterpret_cast<hipStream_t>(stream), "deposit_octree");
+        if (s != PSD_OK) return s;
+    }
     psd::UniformArgs U;
     memset(&U, 0, sizeof(U));
     U.pos = pos;
@@ -329,6 +387,64 @@ psd_status psd_deposit_octree(const float* pos, const psd_particles* p, const ps
                                               (flags & PSD_ACCUMULATE) != 0, tuning_from(opt),
                                               reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) return fail_hip(e, "deposit_octree launch");
+    return PSD_OK;
+}
+
+psd_status psd_octree_coarsen(const psd_octree_node* nodes, int64_t n_nodes, int64_t n_leaves,
+                              int32_t block, int32_t max_level, const float* leaves, float* out,
+                              uint32_t flags, void* stream)
+{
+    if (!nodes || !leaves || !out) return fail(PSD_ERR_ARG, "null pointer");
+    if (block < 1 || block > 1024 || max_level < 0 || max_level > 7)
+        return fail(PSD_ERR_ARG, "bad block or max_level");
+    if (n_nodes < 1 || n_leaves < 1 || n_leaves > n_nodes || n_nodes > psd::octree_max_nodes(max_level))
+        return fail(PSD_ERR_ARG, "bad node or leaf count");
+    if (flags & ~(uint32_t)PSD_OUT_DENSITY) return fail(PSD_ERR_UNSUPPORTED, "flags: PSD_OUT_DENSITY only");
+    if (n_nodes > 1 && (block & 1))
+        return fail(PSD_ERR_UNSUPPORTED, "coarse levels need an even block (2x2x2 cells per coarse cell)");
+    const int64_t cells = (int64_t)block * block * block;
+    const char* lb = reinterpret_cast<const char*>(leaves);
+    const char* ob = reinterpret_cast<const char*>(out);
+    if (lb < ob + n_nodes * cells * 4 && ob < lb + n_leaves * cells * 4)
+        return fail(PSD_ERR_ARG, "out overlaps leaves");
+    hipError_t e = psd::launch_octree_coarsen(reinterpret_cast<const psd::OctNode*>(nodes), n_nodes,
+                                              n_leaves, block, max_level, (flags & PSD_OUT_DENSITY) != 0,
+                                              leaves, out, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail_hip(e, "octree_coarsen");
+    return PSD_OK;
+}
+
+psd_status psd_reorder_workspace_size(const int32_t np[3], size_t* bytes)
+{
+    if (!np || !bytes) return fail(PSD_ERR_ARG, "null pointer");
+    for (int a = 0; a < 3; ++a)
+        if (np[a] < 1) return fail(PSD_ERR_ARG, "bad Lagrangian grid size");
+    if ((double)np[0] * np[1] * np[2] > 4.0e12) return fail(PSD_ERR_ARG, "Lagrangian grid too large");
+    *bytes = psd::reorder_workspace_bytes((int64_t)np[0] * np[1] * np[2]);
+    return PSD_OK;
+}
+
+psd_status psd_reorder_by_id(const int64_t* ids, const float* pos_in, int64_t n, int64_t id_base,
+                             const int32_t np[3], float* pos_out, int64_t* check, void* ws,
+                             size_t ws_bytes, void* stream)
+{
+    if (!np || !pos_out) return fail(PSD_ERR_ARG, "null pointer");
+    if (n < 0 || n > ((int64_t)1 << 42)) return fail(PSD_ERR_ARG, "bad record count");
+    if (n > 0 && (!ids || !pos_in)) return fail(PSD_ERR_ARG, "null pointer");
+    for (int a = 0; a < 3; ++a)
+        if (np[a] < 1) return fail(PSD_ERR_ARG, "bad Lagrangian grid size");
+    if ((double)np[0] * np[1] * np[2] > 4.0e12) return fail(PSD_ERR_ARG, "Lagrangian grid too large");
+    const int64_t slots = (int64_t)np[0] * np[1] * np[2];
+    if (n > 0) {
+        const char* ib = reinterpret_cast<const char*>(pos_in);
+        const char* ob = reinterpret_cast<const char*>(pos_out);
+        if (ib < ob + slots * 12 && ob < ib + n * 12) return fail(PSD_ERR_ARG, "pos_out overlaps pos_in");
+    }
+    if (check && (!ws || ws_bytes < psd::reorder_workspace_bytes(slots)))
+        return fail(PSD_ERR_WORKSPACE, "workspace too small for the check");
+    hipError_t e = psd::launch_reorder_by_id(ids, pos_in, n, id_base, slots, pos_out, check, ws,
+                                             reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail_hip(e, "reorder_by_id");
     return PSD_OK;
 }
 

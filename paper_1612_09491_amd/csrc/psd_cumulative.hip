@@ -180,6 +180,14 @@ __device__ __forceinline__ double zdist_below(const ZDist& Z, double k)
     return k <= Z.s0 ? 0.0 : F;
 }
 
+// Work events of the cumulative walk, counted only by the instrumented
+// kernel instances (psd_options flag PSD_WORK_COUNTERS).
+struct WorkCount {
+    unsigned long long xpiece;  // pieces of the first (u) split
+    unsigned long long piece;   // pieces of the second (v) split: z distributions set up
+    unsigned long long level;   // z levels walked by those pieces
+};
+
 // LDS add with no returned value (one ds_add_f64): the lane does not wait for
 // the old value, as a read-modify-write of its own column would.
 __device__ __forceinline__ void lds_add(double* p, double v)
@@ -196,8 +204,9 @@ __device__ __forceinline__ void lds_add(double* p, double v)
 // step, a quadratic evaluated directly (nothing is carried from level to
 // level, so no error accumulates); the end regions' quadratics have only
 // positive terms.
+template <bool WORK>
 __device__ __forceinline__ void spread_z(const double z[4], double frac, const Tile& t,
-                                         double* Dcol)
+                                         double* Dcol, WorkCount& wc)
 {
     ZDist Z;
     zdist_init(z, Z);
@@ -205,6 +214,7 @@ __device__ __forceinline__ void spread_z(const double z[4], double frac, const T
     const int lA = max(lfirst, t.l0);
     const int lB = min((int)floor(Z.s3), t.l0 + t.tl - 1);
     if (lA > lB) return;
+    if constexpr (WORK) wc.level += (unsigned long long)(lB - lA + 1);
     double Fprev = (lA <= lfirst) ? 0.0 : frac * zdist_below(Z, (double)lA);
     double* p = Dcol + (lA - t.l0);
     double k = (double)(lA + 1);       // upper plane of the level
@@ -271,7 +281,9 @@ __device__ __forceinline__ void spread_z(const double z[4], double frac, const T
 }
 
 // D column (a,b) of one tile: T cut by x <= a+1 and y <= b+1.
-__device__ __forceinline__ void column(const CTet& S, int a, int b, const Tile& t, double* Dcol)
+template <bool WORK>
+__device__ __forceinline__ void column(const CTet& S, int a, int b, const Tile& t, double* Dcol,
+                                       WorkCount& wc)
 {
     for (int l = 0; l < t.tl; ++l) Dcol[l] = 0.0;
     const bool cx = a + 1 < S.ext[0];
@@ -318,6 +330,7 @@ __device__ __forceinline__ void column(const CTet& S, int a, int b, const Tile& 
         W2[c] = a4 ? vd : (a2 ? c3 : c2);
     }
     const int n1 = (a2 || a3) ? 3 : 1;
+    if constexpr (WORK) wc.xpiece += (unsigned long long)n1;
     for (int j = 0; j < n1; ++j) {
         double cv[4][2];
 #pragma unroll
@@ -349,10 +362,11 @@ __device__ __forceinline__ void column(const CTet& S, int a, int b, const Tile& 
         const double u0 = za, u1 = (b3 || b4) ? zb : c0, u2 = (b3 || b4) ? zc : c1;
         const double w0 = b2 ? zb : c0, w1 = b2 ? c2 : c1, w2 = b4 ? zd : (b2 ? c3 : c2);
         const int n2 = (b2 || b3) ? 3 : 1;
+        if constexpr (WORK) wc.piece += (unsigned long long)n2;
         for (int k = 0; k < n2; ++k) {
             const double z[4] = {u0, k == 2 ? w0 : u1, k == 0 ? u2 : w1, w2};
             const double f2 = k == 0 ? s2.f0 : (k == 1 ? s2.f1 : s2.f2);
-            spread_z(z, f1 * f2, t, Dcol);
+            spread_z<WORK>(z, f1 * f2, t, Dcol, wc);
         }
     }
 }
@@ -392,7 +406,8 @@ __device__ __forceinline__ int nth_bit(uint64_t m, int k)
 template <typename OutT>
 __device__ __forceinline__ int setup_tet(const BoxDesc& P, int64_t tid, CTet& S, double& macc,
                                          unsigned long long& n_pair, unsigned long long& n_nz,
-                                         unsigned long long& n_inv, unsigned long long& n_deg)
+                                         unsigned long long& n_inv, unsigned long long& n_deg,
+                                         unsigned long long* stats)
 {
     const int64_t cube = tid / 6;
     const int p = (int)(tid - cube * 6);
@@ -403,7 +418,12 @@ __device__ __forceinline__ int setup_tet(const BoxDesc& P, int64_t tid, CTet& S,
     make_tet(P.pos, P.np[0], P.np[1], P.np[2], P.scale, P.nc, ii, jj, kk, p, T);
     OutT* out = reinterpret_cast<OutT*>(P.out);
     if ((double)kuhn_sign(p) * T.D < 0.0) ++n_inv;
-    if (!(isfinite(T.D) && isfinite(T.l3))) return 0;  // non-finite input: dropped
+    if (!(isfinite(T.D) && isfinite(T.l3))) {
+        // a NaN or infinite vertex cannot be placed: dropped, and counted
+        // (rare, so straight to the counter rather than a register)
+        if (stats) atomicAdd(stats + 7, 1ull);
+        return 0;
+    }
     if (fabs(T.D) <= 1e-12 * T.l3) {
         // zero-volume tetrahedron: all mass to the centroid's cell
         ++n_deg;
@@ -489,7 +509,7 @@ __device__ __forceinline__ void flush_mass(const BoxDesc& P, double& macc)
 // tiles a batch suit small tetrahedra (many per batch), 8 tets with 1408
 // entries large ones (a few fill the buffer).  The 2048-entry instance runs
 // at two per SIMD.
-template <typename OutT, int CAP, int GROUP, int TILES>
+template <typename OutT, int CAP, int GROUP, int TILES, bool WORK>
 __global__ __launch_bounds__(kWave, (CAP <= 1408 ? 3 : 2)) void queue_kernel(QueueArgs Q)
 {
     static_assert(kWave % GROUP == 0 && GROUP <= kWave && TILES <= GROUP, "chunk of whole groups");
@@ -503,6 +523,8 @@ __global__ __launch_bounds__(kWave, (CAP <= 1408 ? 3 : 2)) void queue_kernel(Que
     const int lane = threadIdx.x;
     double macc = 0.0;
     unsigned long long n_tet = 0, n_pair = 0, n_col = 0, n_nz = 0, n_inv = 0, n_deg = 0;
+    WorkCount wc = {0ull, 0ull, 0ull};
+    unsigned long long n_colcell = 0;
     int cur_box = -1;
     BoxDesc P = Q.box0;
 
@@ -545,7 +567,8 @@ __global__ __launch_bounds__(kWave, (CAP <= 1408 ? 3 : 2)) void queue_kernel(Que
         int ncell = 0;
         if (lane < GROUP && k < ntodo) {
             const int64_t tid = first + (P.exact_mask ? nth_bit(todo, k) : k);
-            ncell = setup_tet<OutT>(P, tid, slots[lane], macc, n_pair, n_nz, n_inv, n_deg);
+            ncell = setup_tet<OutT>(P, tid, slots[lane], macc, n_pair, n_nz, n_inv, n_deg,
+                                    Q.stats);
         }
         if (lane < GROUP) slots[lane].ncell = ncell;
         __syncthreads();
@@ -675,8 +698,9 @@ __global__ __launch_bounds__(kWave, (CAP <= 1408 ? 3 : 2)) void queue_kernel(Que
                         const int qa = fdivi(r, t.inv_wb);
                         const int a = t.a0 - t.ha + qa;
                         const int b = t.b0 - t.hb + (r - qa * wb);
-                        column(S, a, b, t, Dbuf + t.doff + r * t.tl);
+                        column<WORK>(S, a, b, t, Dbuf + t.doff + r * t.tl, wc);
                         ++n_col;
+                        if constexpr (WORK) n_colcell += (unsigned long long)t.tl;
                     }
                     __syncthreads();
                     // Phase 2: the cells (i, j, l) of this lane's column, l
@@ -807,6 +831,12 @@ __global__ __launch_bounds__(kWave, (CAP <= 1408 ? 3 : 2)) void queue_kernel(Que
         n_tet += __shfl_xor(n_tet, off, kWave);
         n_pair += __shfl_xor(n_pair, off, kWave);
         n_col += __shfl_xor(n_col, off, kWave);
+        if constexpr (WORK) {
+            wc.xpiece += __shfl_xor(wc.xpiece, off, kWave);
+            wc.piece += __shfl_xor(wc.piece, off, kWave);
+            wc.level += __shfl_xor(wc.level, off, kWave);
+            n_colcell += __shfl_xor(n_colcell, off, kWave);
+        }
         n_nz += __shfl_xor(n_nz, off, kWave);
         n_inv += __shfl_xor(n_inv, off, kWave);
         n_deg += __shfl_xor(n_deg, off, kWave);
@@ -815,6 +845,12 @@ __global__ __launch_bounds__(kWave, (CAP <= 1408 ? 3 : 2)) void queue_kernel(Que
         atomicAdd(Q.stats + 0, n_tet);
         atomicAdd(Q.stats + 1, n_pair);
         atomicAdd(Q.stats + 2, n_col);
+        if constexpr (WORK) {
+            atomicAdd(Q.stats + 8, wc.xpiece);
+            atomicAdd(Q.stats + 9, wc.piece);
+            atomicAdd(Q.stats + 10, wc.level);
+            atomicAdd(Q.stats + 11, n_colcell);
+        }
         atomicAdd(Q.stats + 3, n_nz);
         atomicAdd(Q.stats + 4, n_inv);
         atomicAdd(Q.stats + 5, n_deg);
@@ -921,27 +957,28 @@ QueueLayout queue_layout(int64_t n_chunks, int n_boxes, bool ordered)
     return L;
 }
 
-// Kernel instances by buffer size: (entries, tets per group).
-template <typename OutT>
+// Kernel instances by buffer size: (entries, tets per group, tiles per
+// batch), plain or counting the walk's work events.
+template <typename OutT, bool WORK>
 const void* queue_kernel_for(int cap)
 {
-    if (cap <= 512) return reinterpret_cast<const void*>(&queue_kernel<OutT, 512, 16, 16>);
-    if (cap <= 960) return reinterpret_cast<const void*>(&queue_kernel<OutT, 960, 32, 16>);
-    if (cap <= 1408) return reinterpret_cast<const void*>(&queue_kernel<OutT, 1408, 8, 8>);
-    return reinterpret_cast<const void*>(&queue_kernel<OutT, 2048, 32, 32>);
+    if (cap <= 512) return reinterpret_cast<const void*>(&queue_kernel<OutT, 512, 16, 16, WORK>);
+    if (cap <= 960) return reinterpret_cast<const void*>(&queue_kernel<OutT, 960, 32, 16, WORK>);
+    if (cap <= 1408) return reinterpret_cast<const void*>(&queue_kernel<OutT, 1408, 8, 8, WORK>);
+    return reinterpret_cast<const void*>(&queue_kernel<OutT, 2048, 32, 32, WORK>);
 }
 
-template <typename OutT>
+template <typename OutT, bool WORK>
 hipError_t launch_queue_kernel(const QueueArgs& Q, int cap, int grid, hipStream_t stream)
 {
     if (cap <= 512)
-        hipLaunchKernelGGL((queue_kernel<OutT, 512, 16, 16>), dim3(grid), dim3(kWave), 0, stream, Q);
+        hipLaunchKernelGGL((queue_kernel<OutT, 512, 16, 16, WORK>), dim3(grid), dim3(kWave), 0, stream, Q);
     else if (cap <= 960)
-        hipLaunchKernelGGL((queue_kernel<OutT, 960, 32, 16>), dim3(grid), dim3(kWave), 0, stream, Q);
+        hipLaunchKernelGGL((queue_kernel<OutT, 960, 32, 16, WORK>), dim3(grid), dim3(kWave), 0, stream, Q);
     else if (cap <= 1408)
-        hipLaunchKernelGGL((queue_kernel<OutT, 1408, 8, 8>), dim3(grid), dim3(kWave), 0, stream, Q);
+        hipLaunchKernelGGL((queue_kernel<OutT, 1408, 8, 8, WORK>), dim3(grid), dim3(kWave), 0, stream, Q);
     else
-        hipLaunchKernelGGL((queue_kernel<OutT, 2048, 32, 32>), dim3(grid), dim3(kWave), 0, stream, Q);
+        hipLaunchKernelGGL((queue_kernel<OutT, 2048, 32, 32, WORK>), dim3(grid), dim3(kWave), 0, stream, Q);
     return hipGetLastError();
 }
 
@@ -953,6 +990,7 @@ Tuning default_tuning()
     t.cap = 0;           // chosen from the boxes (auto_cap)
     t.waves_per_cu = 0;  // as many as fit a compute unit
     t.ordered = 0;
+    t.work_counters = 0;
     return t;
 }
 
@@ -970,19 +1008,23 @@ int auto_cap(const BoxDesc* boxes, int n_boxes)
     return ratio >= 1.5 ? 1408 : 960;
 }
 
-hipError_t queue_resident_waves(int cap, bool out_fp64, int& waves)
+hipError_t queue_resident_waves(int cap, bool out_fp64, int& waves, bool work)
 {
-    // one kernel instance per (buffer size, output type); the answer only
-    // depends on the instance, so it is asked once
-    static std::atomic<int> known[4][2];
+    // one kernel instance per (buffer size, output type, counters); the
+    // answer only depends on the instance, so it is asked once
+    static std::atomic<int> known[4][2][2];
     const int ci = cap <= 512 ? 0 : (cap <= 960 ? 1 : (cap <= 1408 ? 2 : 3)), ti = out_fp64 ? 1 : 0;
-    int n = known[ci][ti].load(std::memory_order_relaxed);
+    const int wi = work ? 1 : 0;
+    int n = known[ci][ti][wi].load(std::memory_order_relaxed);
     if (n == 0) {
-        const void* k = out_fp64 ? queue_kernel_for<double>(cap) : queue_kernel_for<float>(cap);
+        const void* k = out_fp64 ? (work ? queue_kernel_for<double, true>(cap)
+                                         : queue_kernel_for<double, false>(cap))
+                                 : (work ? queue_kernel_for<float, true>(cap)
+                                         : queue_kernel_for<float, false>(cap));
         const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, kWave, 0);
         if (e != hipSuccess) return e;
         if (n < 1) n = 1;
-        known[ci][ti].store(n, std::memory_order_relaxed);
+        known[ci][ti][wi].store(n, std::memory_order_relaxed);
     }
     waves = n;
     return hipSuccess;
@@ -1004,7 +1046,17 @@ hipError_t launch_queue(const BoxDesc* boxes_in, int n_boxes, bool out_fp64, con
                         void* ws, size_t ws_bytes, unsigned long long* stats, hipStream_t stream)
 {
     if (n_boxes < 1) return hipErrorInvalidValue;
-    std::vector<BoxDesc> boxes(boxes_in, boxes_in + n_boxes);
+    // a plain grid or an octree's levels fit the local table: no host
+    // allocation on those paths
+    BoxDesc local[8];
+    std::vector<BoxDesc> many;
+    BoxDesc* boxes = local;
+    if (n_boxes > 8) {
+        many.assign(boxes_in, boxes_in + n_boxes);
+        boxes = many.data();
+    } else {
+        for (int b = 0; b < n_boxes; ++b) local[b] = boxes_in[b];
+    }
     int64_t n_chunks = 0;
     for (int b = 0; b < n_boxes; ++b) {
         boxes[b].chunk_begin = n_chunks;
@@ -1023,7 +1075,7 @@ hipError_t launch_queue(const BoxDesc* boxes_in, int n_boxes, bool out_fp64, con
     Q.stats = stats;
     hipError_t e;
     if (n_boxes > 1) {
-        e = hipMemcpyAsync(base + L.boxes, boxes.data(), sizeof(BoxDesc) * (size_t)n_boxes,
+        e = hipMemcpyAsync(base + L.boxes, boxes, sizeof(BoxDesc) * (size_t)n_boxes,
                            hipMemcpyHostToDevice, stream);
         if (e != hipSuccess) return e;
         Q.boxes = reinterpret_cast<const BoxDesc*>(base + L.boxes);
@@ -1050,17 +1102,21 @@ hipError_t launch_queue(const BoxDesc* boxes_in, int n_boxes, bool out_fp64, con
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         cus < 1)
         cus = 256;
-    const int cap = tune.cap > 0 ? tune.cap : auto_cap(boxes.data(), n_boxes);
+    const int cap = tune.cap > 0 ? tune.cap : auto_cap(boxes, n_boxes);
+    const bool work = tune.work_counters != 0 && stats != nullptr;
     int waves = tune.waves_per_cu;
     if (waves <= 0) {
-        const hipError_t e = queue_resident_waves(cap, out_fp64, waves);
+        const hipError_t e = queue_resident_waves(cap, out_fp64, waves, work);
         if (e != hipSuccess) return e;
     }
     int64_t grid = (int64_t)cus * waves;
     if (grid > n_chunks) grid = n_chunks;
     if (grid < 1) grid = 1;
-    return out_fp64 ? launch_queue_kernel<double>(Q, cap, (int)grid, stream)
-                    : launch_queue_kernel<float>(Q, cap, (int)grid, stream);
+    if (work)
+        return out_fp64 ? launch_queue_kernel<double, true>(Q, cap, (int)grid, stream)
+                        : launch_queue_kernel<float, true>(Q, cap, (int)grid, stream);
+    return out_fp64 ? launch_queue_kernel<double, false>(Q, cap, (int)grid, stream)
+                    : launch_queue_kernel<float, false>(Q, cap, (int)grid, stream);
 }
 
 }  // namespace psd

@@ -70,6 +70,7 @@ struct Tuning {
                         // (0: chosen from the boxes' cells per Lagrangian spacing)
     int waves_per_cu;   // persistent workgroups per compute unit (0: as many as fit)
     int ordered;        // 1: chunks in decreasing estimated cost
+    int work_counters;  // 1: the instrumented kernel, adding work events into stats[8..11]
 };
 
 struct QueueArgs {
@@ -93,7 +94,13 @@ hipError_t launch_queue(const BoxDesc* boxes, int n_boxes, bool out_fp64, const 
                         void* ws, size_t ws_bytes, unsigned long long* stats, hipStream_t stream);
 Tuning default_tuning();
 // Wavefronts of the deposit kernel with this buffer that fit one compute unit.
-hipError_t queue_resident_waves(int cap, bool out_fp64, int& waves);
+hipError_t queue_resident_waves(int cap, bool out_fp64, int& waves, bool work = false);
+
+// Number of NaN or infinite values among p[0..n) (a device array), counted
+// on `stream` into the device word dcount and returned in host_count;
+// synchronizes the stream.
+hipError_t count_nonfinite(const float* p, int64_t n, unsigned long long* dcount,
+                           hipStream_t stream, unsigned long long& host_count);
 
 // ---------------------------------------------------------------------------
 // Octree (Section 4)
@@ -139,6 +146,21 @@ size_t octree_queue_bytes(const OctreeArgs& A);
 hipError_t launch_deposit_octree(const OctreeArgs& A, const UniformArgs& base, const OctNode* nodes,
                                  int64_t n_nodes, int64_t n_leaf_cells, void* ws, size_t ws_bytes,
                                  bool accumulate, const Tuning& tune, hipStream_t stream);
+
+// Coarse levels: every node's B^3 block, leaves copied, internal nodes as
+// 2x2x2 sums (averages for densities) of their children, bottom-up.
+hipError_t launch_octree_coarsen(const OctNode* nodes, int64_t n_nodes, int64_t n_leaves, int B,
+                                 int max_level, bool density, const float* leaves, float* out,
+                                 hipStream_t stream);
+
+// ---------------------------------------------------------------------------
+// Snapshot ingest
+// ---------------------------------------------------------------------------
+
+size_t reorder_workspace_bytes(int64_t n_slots);
+hipError_t launch_reorder_by_id(const int64_t* ids, const float* pos_in, int64_t n, int64_t id_base,
+                                int64_t n_slots, float* pos_out, int64_t* check, void* ws,
+                                hipStream_t stream);
 
 // ---------------------------------------------------------------------------
 // Learned overlap surrogate

@@ -210,7 +210,8 @@ __global__ __launch_bounds__(kWave) void deposit_uniform_kernel(UniformArgs P)
             // Non-finite input cannot be placed; such a tetrahedron is dropped.
             const bool finite_tet = isfinite(T.D) && isfinite(T.l3);
             if (!finite_tet) {
-                // nothing deposited
+                // nothing deposited; counted
+                if (P.stats) atomicAdd(P.stats + 7, 1ull);
             } else if (fabs(T.D) <= 1e-12 * T.l3) {
                 // zero-volume tetrahedron: all mass to the centroid's cell
                 ++n_deg;

@@ -134,3 +134,29 @@ def test_octree_leaf_side_limit(psd):
     with pytest.raises(psd.PsdError) as e:
         psd.octree_workspace_size((8, 8, 8), block=1025, max_level=0)
     assert e.value.code == psd.PSD_ERR_ARG
+
+
+def test_wrapper_rejects_bad_side_outputs(psd):
+    """Mass sums and counters receive 8-byte device atomics: anything that is not a CUDA
+    float64 (int64) tensor of the right length is refused before a call is made."""
+    import torch
+    with pytest.raises(ValueError):
+        psd._check_aux(torch.zeros(1, dtype=torch.float32), 1, None)
+    with pytest.raises(ValueError):
+        psd._check_aux(torch.zeros(1, dtype=torch.float64), 1, None)  # host memory
+    with pytest.raises(ValueError):
+        psd._check_aux(None, 1, torch.zeros(8, dtype=torch.int32))
+    with pytest.raises(ValueError):
+        psd._check_aux(None, 1, torch.zeros(4, dtype=torch.int64))
+    with pytest.raises(ValueError):
+        psd._check_aux(None, 1, torch.zeros(8, dtype=torch.int64))  # host memory
+    with pytest.raises(ValueError):
+        psd._workspace(torch.zeros(16, dtype=torch.uint8), 8, None)  # host memory
+    psd._check_aux(None, 3, None)
+
+
+def test_check_finite_flag_is_accepted(psd):
+    """PSD_CHECK_FINITE is a known flag of every deposit; unknown bits are refused."""
+    assert psd.PSD_CHECK_FINITE == 1 << 5
+    assert psd.uniform_workspace_size((8, 8, 8), 16, flags=psd.PSD_CHECK_FINITE) > 0
+    assert psd.STAT_NAMES[7] == "dropped_nonfinite"

@@ -135,19 +135,53 @@ def test_huge_stretched_tets(psd, orc):
     _compare(psd, orc, pos, 48)
 
 
+def _max_bbox_cells(orc, pos, nc):
+    """Largest bounding-box cell count over the tetrahedra (oracle's unwrapped vertices)."""
+    n = pos.shape[0]
+    best = 0
+    for i in range(n):
+        for j in range(n):
+            for k in range(n):
+                v, _ = orc.cube_tets(pos, (nc, nc, nc), i, j, k)
+                e = np.floor(v.max(axis=1)) - np.floor(v.min(axis=1)) + 1
+                best = max(best, int(np.prod(e, axis=1).max()))
+    return best
+
+
 @pytest.mark.parametrize("tuning", [(512, 0, 0), (960, 0, 1), (1408, 0, 0), (2048, 0, 0)])
 def test_huge_tets_tiled_in_every_instance(psd, orc, tuning):
     # tets of thousands of bbox cells are tiled with halo columns; in the 16-tet
     # instances they also interrupt the all-lanes planning of untiled runs
     pos = zeldovich_positions(4, 1.4, seed=44)
+    # the input has tetrahedra whose bbox (the D array of the walk) exceeds the
+    # instance's LDS buffer, so the tiled walk runs
+    biggest = _max_bbox_cells(orc, pos, 48)
+    assert biggest > tuning[0], (biggest, tuning)
     ref, _ = orc.deposit_uniform(pos, 48)
     dev = torch.device("cuda:0")
     pt = torch.from_numpy(pos).to(dev)
     st = torch.zeros(8, dtype=torch.int64, device=dev)
     out = psd.deposit_uniform(pt, 48, flags=psd.PSD_PREC_FP64, stats=st, tuning=tuning)
     assert _rel_l1(out.cpu().numpy(), ref) <= FP64_L1
-    # more cells than the buffer in some tetrahedron: the tiled walk ran
-    assert int(st[1].item()) > 0
+    assert int(st[0].item()) == 6 * 4 ** 3
+
+
+def test_zel64_g16_full_grid(psd, orc):
+    """64^3 particles (rms 2 spacings) onto 16^3 cells, 0.25 cells per spacing: the
+    geometry of the surrogate's workload at a size the oracle finishes in seconds;
+    whole grid, FP32 and FP64 outputs."""
+    pos, p = workload("zel64_g16")
+    ref, cnt = orc.deposit_uniform(pos, p["nc"])
+    got, msum, st = _run(psd, pos, p["nc"])
+    l1, linf = _rel_l1(got, ref), _rel_linf(got, ref)
+    print(f"zel64_g16 FP32 grid: L1 {l1:.3e} Linf {linf:.3e}")
+    assert l1 <= FP32_L1 and linf <= FP32_LINF
+    assert abs(msum - 1.0) <= 1e-12
+    _check_stats(st, cnt)
+    got64, msum64, _ = _run(psd, pos, p["nc"], flags=psd.PSD_PREC_FP64)
+    l1, linf = _rel_l1(got64, ref), _rel_linf(got64, ref)
+    print(f"zel64_g16 FP64 grid: L1 {l1:.3e} Linf {linf:.3e}")
+    assert l1 <= FP64_L1 and linf <= FP64_LINF
 
 
 def test_flat_tets_go_to_centroid_cell(psd, orc):
@@ -215,13 +249,13 @@ def test_zel256_g512_sampled_blocks(psd, orc, method):
     assert abs(msum - 1.0) <= 1e-6
     assert abs(got.sum() - 1.0) <= 1e-5
     rng = np.random.default_rng(2)
-    for _ in range(2):
+    for _ in range(8):
         lo = [int(x) for x in rng.integers(0, nc - 16, size=3)]
         ref, _ = orc.deposit_uniform(pos, nc, region=(lo, (16, 16, 16)))
         blk = got[lo[0]:lo[0] + 16, lo[1]:lo[1] + 16, lo[2]:lo[2] + 16]
-        l1 = _rel_l1(blk, ref)
-        print(f"block {lo}: L1 {l1:.3e} Linf {_rel_linf(blk, ref):.3e}")
-        assert l1 <= FP32_L1
+        l1, linf = _rel_l1(blk, ref), _rel_linf(blk, ref)
+        print(f"block {lo}: L1 {l1:.3e} Linf {linf:.3e}", flush=True)
+        assert l1 <= FP32_L1 and linf <= FP32_LINF
 
 
 @pytest.mark.parametrize("nc", [64, 20])
@@ -239,3 +273,29 @@ def test_kernel_instances_agree(psd, orc, nc):
         got = out.cpu().numpy()
         assert _rel_l1(got, ref) <= FP64_L1, (tuning, _rel_l1(got, ref))
         assert abs(float(ms.item()) - 1.0) <= 1e-12
+
+
+@pytest.mark.parametrize("cap", [1408, 960])
+def test_work_counters_match_cost_model(psd, orc, cap):
+    """The instrumented kernel's work events (PSD_WORK_COUNTERS) equal the CPU replay of
+    the cumulative walk in costmodel.py on every tetrahedron of 32^3 -> 64^3; the split
+    and level counts may differ only where rounding decides an on-plane vertex.  Its grid
+    is held to the same parity bar as the plain kernel's."""
+    import costmodel
+    pos, p = workload("zel32_g64", seed=1)
+    dev = torch.device("cuda:0")
+    pt = torch.from_numpy(pos).to(dev)
+    st = torch.zeros(16, dtype=torch.int64, device=dev)
+    out = psd.deposit_uniform(pt, p["nc"], flags=psd.PSD_WORK_COUNTERS, stats=st,
+                              tuning=(cap, 0, 0))
+    torch.cuda.synchronize()
+    s = st.cpu().numpy()
+    cm = costmodel.count_events(pos, p["nc"], np.arange(32 ** 3), cap=cap)
+    gpu = {"column": s[2], "xpiece": s[8], "piece": s[9], "level": s[10], "colcell": s[11]}
+    print({k: (int(v), cm[k]) for k, v in gpu.items()})
+    assert gpu["column"] == cm["column"] and gpu["colcell"] == cm["colcell"]
+    for k in ("xpiece", "piece", "level"):
+        assert abs(int(gpu[k]) - cm[k]) <= 1e-5 * cm[k] + 2, k
+    ref, _ = orc.deposit_uniform(pos, p["nc"])
+    got = out.double().cpu().numpy()
+    assert _rel_l1(got, ref) <= FP32_L1 and _rel_linf(got, ref) <= FP32_LINF

@@ -148,8 +148,21 @@ def test_monte_carlo_fractions(orc):
                 assert abs(k - n * p) <= 5 * sd, (a, b, c, k, n * p)
 
 
-def test_paper_scheme_counts_are_positive(orc):
-    """The paper-scheme clip reports work for a cell that cuts the tetrahedron."""
-    v = np.array([[0.2, 0.2, 0.2], [2.5, 0.3, 0.1], [0.4, 2.2, 0.3], [0.1, 0.5, 2.9]])
-    V, pv, cut, sub = orc.clip_tet_box_paper(v, np.zeros(3), np.ones(3))
-    assert V > 0 and pv > 0 and cut > 0 and sub > 0
+def test_paper_scheme_counts_hand_counted(orc):
+    """Visits, edge cuts and sub-tetrahedra of the paper-scheme clip (Section 6.3) equal
+    the hand counts of the golden file: a tetrahedron inside the cell, the corner simplex
+    at a = 3/2, and the identity Freudenthal tetrahedron of a side-2 cube in each of its
+    8 cells.  These counts price the paper's algorithmic work, so a double-counted visit
+    or a miscounted prism cut fails here."""
+    cases = {
+        "A": np.array([[0.1, 0.1, 0.1], [0.5, 0.1, 0.1], [0.1, 0.5, 0.1], [0.1, 0.1, 0.5]]),
+        "B": np.array([[0, 0, 0], [1.5, 0, 0], [0, 1.5, 0], [0, 0, 1.5]], float),
+        "C": np.array([[0, 0, 0], [2, 0, 0], [2, 2, 0], [2, 2, 2]], float),
+    }
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "paper_scheme_counts.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 10
+    for case, x, y, z, visits, cuts, subs in rows:
+        lo = np.array([int(x), int(y), int(z)], float)
+        _, pv, cut, sub = orc.clip_tet_box_paper(cases[case], lo, lo + 1)
+        assert (pv, cut, sub) == (int(visits), int(cuts), int(subs)), (case, x, y, z)
