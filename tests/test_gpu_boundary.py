@@ -61,7 +61,9 @@ def test_uniform_drops_and_counts_without_the_flag(psd, orc, method):
     s = st.cpu().numpy()
     m = 1.0 / (6 * 8 ** 3)
     assert s[7] == 24 and s[0] == 6 * 8 ** 3
-    assert abs(float(ms.item()) - (1.0 - 24 * m)) <= 1e-12
+    # the per-cell method sums its FP32 cell values in FP64; the default sums FP64 pieces
+    tol = 1e-12 if method == 0 else 1e-6
+    assert abs(float(ms.item()) - (1.0 - 24 * m)) <= tol
     got = out.double().cpu().numpy()
     assert np.isfinite(got).all()
     assert abs(got.sum() - (1.0 - 24 * m)) <= 1e-5
