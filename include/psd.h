@@ -155,6 +155,28 @@ psd_status psd_deposit_uniform(const float* pos, const psd_particles* p, const i
                                void* out, double* mass_sum, const psd_options* opt, void* ws,
                                size_t ws_bytes, void* stream);
 
+/*
+ * psd_deposit_uniform without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, flags, results and
+ * errors as psd_deposit_uniform; the workspace is a fixed device array of
+ * PSD_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held until the
+ * process ends.  The call allocates nothing.
+ *   Limit: problems whose psd_uniform_workspace_size exceeds
+ *   PSD_NOALLOC_SCRATCH_BYTES fail with PSD_ERR_WORKSPACE (index order needs
+ *   256 bytes at any size; PSD_SURROGATE adds 8 bytes per 64 tetrahedra, so
+ *   up to about 134M tetrahedra; cost ordering adds 12 bytes per 64).
+ *   Every call on one GPU shares that GPU's array: calls that overlap in
+ *   time on one GPU (several streams or host threads) race and give wrong
+ *   results; serialise them.  The array keeps the last call's contents; the
+ *   call clears what must start at zero.
+ * Runs on the current device; `stream` must belong to it.
+ */
+enum { PSD_NOALLOC_SCRATCH_BYTES = 16 << 20 };
+psd_status psd_deposit_uniform_noalloc(const float* pos, const psd_particles* p,
+                                       const int32_t nc[3], void* out, double* mass_sum,
+                                       const psd_options* opt, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Many independent boxes in one launch                                      */
 /* ------------------------------------------------------------------------ */

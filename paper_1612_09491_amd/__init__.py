@@ -205,6 +205,45 @@ def deposit_uniform(pos: torch.Tensor, nc, box: float = 1.0, mass: float = 1.0, 
     return out
 
 
+PSD_NOALLOC_SCRATCH_BYTES = 16 << 20
+
+
+def deposit_uniform_noalloc(pos: torch.Tensor, nc, box: float = 1.0, mass: float = 1.0,
+                            flags: int = 0, out: torch.Tensor | None = None,
+                            mass_sum: torch.Tensor | None = None,
+                            stats: torch.Tensor | None = None, stream=None, tuning=None,
+                            surrogate: torch.Tensor | None = None) -> torch.Tensor:
+    """``deposit_uniform`` through psd_deposit_uniform_noalloc: the library's fixed
+    per-GPU scratch array serves as the workspace, so the call allocates nothing
+    on the device when ``out`` is given.  Calls that overlap in time on one GPU
+    race on that array.  Problems needing more than PSD_NOALLOC_SCRATCH_BYTES of
+    workspace raise PsdError (PSD_ERR_WORKSPACE)."""
+    L = lib()
+    if not getattr(L, "_noalloc_bound", False):
+        L.psd_deposit_uniform_noalloc.restype = C.c_int
+        L.psd_deposit_uniform_noalloc.argtypes = [C.c_void_p, C.POINTER(Particles),
+                                                  C.POINTER(C.c_int32), C.c_void_p, C.c_void_p,
+                                                  C.POINTER(Options), C.c_void_p]
+        L._noalloc_bound = True
+    if surrogate is not None:
+        _check_params(surrogate)
+    p = _particles(pos, box, mass)
+    g = _grid3(nc)
+    dtype = torch.float64 if flags & PSD_PREC_FP64 else torch.float32
+    if out is None:
+        out = torch.empty(g, dtype=dtype, device=pos.device)
+    elif out.dtype != dtype or tuple(out.shape) != g or not out.is_contiguous() or not out.is_cuda:
+        raise ValueError(f"out must be a contiguous CUDA {dtype} tensor of shape {g}")
+    _check_aux(mass_sum, 1, stats, flags)
+    o = _options(flags, stats, tuning, surrogate)
+    ncs = (C.c_int32 * 3)(*g)
+    _check(L.psd_deposit_uniform_noalloc(pos.data_ptr(), C.byref(p), ncs, out.data_ptr(),
+                                         mass_sum.data_ptr() if mass_sum is not None else None,
+                                         C.byref(o), _stream_handle(stream)),
+           "psd_deposit_uniform_noalloc")
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Octree
 # ---------------------------------------------------------------------------
