@@ -134,7 +134,7 @@ def _tile_shape(ext, cap):
     return ta, tb, tl
 
 
-def count_events(pos: np.ndarray, nc, cubes: np.ndarray, cap: int = 1408,
+def count_events(pos: np.ndarray, nc, cubes: np.ndarray, cap: int = 1024,
                  batch_tets: int = 4000) -> dict:
     """Work events of the cumulative kernel with a `cap`-entry LDS buffer on the
     tetrahedra of the listed Lagrangian cubes (positions float32 [np0, np1, np2, 3],

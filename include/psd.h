@@ -94,12 +94,16 @@ typedef struct {
 typedef struct {
     int32_t lds_cap;      /* FP64 entries of the per-wavefront LDS buffer:
                              512 (16-tet groups), 960 (32 tets set up at
-                             once, 16 tiles a batch), 1408 (8-tet groups) or
-                             2048 (32-tet groups); 0 = 1408 when every box has >= 1.5 grid
-                             cells per Lagrangian spacing (large tets), else
-                             960; octree leaves always 960                    */
+                             once, 16 tiles a batch), 1024 (8-tet groups, the
+                             pieces of all columns walked 64 at a time from a
+                             ring), 1408 (8-tet groups, each column's pieces
+                             on its own lane) or 2048 (32-tet groups); 0 =
+                             1024 when every box has >= 1.5 grid cells per
+                             Lagrangian spacing (large tets), else 960;
+                             octree leaves always 960                         */
     int32_t waves_per_cu; /* persistent wavefronts per compute unit (0 = as
-                             many as fit: 12 at 960 or 1408 entries on gfx950) */
+                             many as fit: 12 at 960, 1024 or 1408 entries on
+                             gfx950)                                          */
     int32_t ordered;      /* 1: process 64-tet chunks in decreasing estimated
                              cost (bbox cells); 0: in index order             */
     int32_t reserved;     /* must be 0                                        */
@@ -210,7 +214,7 @@ psd_status psd_deposit_batched(const psd_box* boxes, int32_t n_boxes, double* ma
 
 /*
  * Chooses the launch shape (psd_tuning) of psd_deposit_batched for this batch
- * by timing candidates with HIP events on `stream`: LDS buffer of 960, 1408
+ * by timing candidates with HIP events on `stream`: LDS buffer of 960, 1024
  * or 2048 FP64 entries, all the wavefronts that fit a compute unit or half
  * of them, chunks in index or cost order.  The boxes' outputs are overwritten with a valid deposit.  If
  * cache_path (host string, may be NULL) names a JSON file, a result for the
@@ -337,7 +341,9 @@ psd_status psd_reorder_workspace_size(const int32_t np[3], size_t* bytes);
  *   np        host, the Lagrangian grid size (each >= 1)
  *   pos_out   DEVICE float [np0][np1][np2][3]; must not overlap pos_in; slots
  *             that no record names keep their contents; when several records
- *             name one slot, one of them (unspecified) is stored
+ *             name one slot and `check` is given, one of them (unspecified)
+ *             is stored whole; without `check` the slot then holds an
+ *             unspecified mix of their coordinates (three separate stores)
  *   check     DEVICE int64[3] or NULL: set to [0] records whose id is outside
  *             [id_base, id_base + np0 np1 np2) (skipped), [1] records naming a
  *             slot another record already named, [2] slots no record names.

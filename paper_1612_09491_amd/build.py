@@ -15,6 +15,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpsd.so")
+# measurement microbenchmarks (atomic and LDS rates), a library of their own
+PEAKS_LIB = os.path.join(HERE, "libpsd_peaks.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -63,7 +65,20 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         print(" ".join(link), flush=True)
     subprocess.run(link, check=True)
     os.replace(tmp, LIB)
+    build_peaks(verbose)
     return LIB
+
+
+def build_peaks(verbose: bool = False) -> str:
+    """The microbenchmark library the benchmark prices the deposit's atomics with."""
+    srcs = sorted(glob.glob(os.path.join(CSRC, "peaks", "*.hip")))
+    tmp = PEAKS_LIB + ".tmp"
+    cmd = [HIPCC, *COMMON, "-shared", "-o", tmp, *srcs]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, PEAKS_LIB)
+    return PEAKS_LIB
 
 
 if __name__ == "__main__":

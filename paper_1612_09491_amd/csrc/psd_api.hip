@@ -75,7 +75,8 @@ bool tuning_ok(const psd_options* opt)
 {
     if (!opt || !opt->tuning) return true;
     const psd_tuning* u = opt->tuning;
-    return (u->lds_cap == 0 || u->lds_cap == 512 || u->lds_cap == 960 || u->lds_cap == 1408 ||
+    return (u->lds_cap == 0 || u->lds_cap == 512 || u->lds_cap == 960 || u->lds_cap == 1024 ||
+            u->lds_cap == 1408 ||
             u->lds_cap == 2048) &&
            u->waves_per_cu >= 0 && u->waves_per_cu <= 64 && u->reserved == 0;
 }
@@ -293,7 +294,7 @@ psd_status psd_autotune_batched(const psd_box* boxes, int32_t n_boxes, const psd
     if (flags & ~kBatchedFlags) return fail(PSD_ERR_UNSUPPORTED, "unsupported flags");
     if (!ws || ws_bytes < psd::batched_ws_bytes(boxes, n_boxes, true))
         return fail(PSD_ERR_WORKSPACE, "workspace too small (size it for ordered chunks)");
-    psd::Tuning t;
+    psd::Tuning t = psd::default_tuning();
     double ms = 0.0;
     hipError_t e = psd::autotune_batched(boxes, n_boxes, flags & PSD_OUT_DENSITY, ws, ws_bytes,
                                          reinterpret_cast<hipStream_t>(stream), cache_path, t, ms);

@@ -117,7 +117,7 @@ static bool cache_lookup(const char* path, const std::string& key, Tuning& t, do
     c = (int)dc;
     w = (int)dw;
     o = (int)dord;
-    if (!(c == 512 || c == 960 || c == 1408 || c == 2048) || w < 1 || w > 64) return false;
+    if (!(c == 512 || c == 960 || c == 1024 || c == 1408 || c == 2048) || w < 1 || w > 64) return false;
     t.cap = c;
     t.waves_per_cu = w;
     t.ordered = o ? 1 : 0;
@@ -185,7 +185,7 @@ hipError_t autotune_batched(const psd_box* boxes, int n, uint32_t flags, void* w
         if (cache_lookup(cache_path, key, best, best_ms)) return hipSuccess;
     }
     const bool density = (flags & PSD_OUT_DENSITY) != 0;
-    const int caps[3] = {960, 1408, 2048};
+    const int caps[3] = {960, 1024, 2048};
     hipEvent_t e0, e1;
     hipError_t e = hipEventCreate(&e0);
     if (e != hipSuccess) return e;
@@ -201,7 +201,7 @@ hipError_t autotune_batched(const psd_box* boxes, int n, uint32_t flags, void* w
     for (int ord = 0; ord < 2 && e == hipSuccess; ++ord)
         for (int ci = 0; ci < 3 && e == hipSuccess; ++ci)
             for (int wi = 0; wi < 2 && e == hipSuccess; ++wi) {
-                Tuning t;
+                Tuning t = default_tuning();
                 t.cap = caps[ci];
                 int fit = 1;
                 e = queue_resident_waves(t.cap, false, fit);

@@ -372,6 +372,167 @@ __device__ __forceinline__ void column(const CTet& S, int a, int b, const Tile& 
 }
 
 
+// Pieces of the two-plane splits waiting for their z walk: a ring of QCAP
+// records in LDS (QCAP a power of two), one per piece: its four vertex
+// heights, its volume fraction of the tetrahedron, and where its levels go
+// (D-buffer offset of its column and tile index, packed).  Every lane of the
+// wavefront produces the pieces of its own column, 0 to 9 of them; the z
+// walks then go over the lanes 64 pieces at a time, so a column cut into nine
+// pieces no longer holds the other 63 lanes back.
+template <int QCAP>
+struct PieceRing {
+    double z[4][QCAP];
+    double frac[QCAP];
+    int where[QCAP];  // D offset << 8 | tile
+};
+
+// The z walks of the next min(count, 64) queued pieces, one per lane.
+// Wave-uniform: every lane calls it with the same head and count.
+template <bool WORK, int QCAP>
+__device__ __forceinline__ void drain_round(PieceRing<QCAP>& Q, int& head, int& count,
+                                            const Tile* tiles, double* Dbuf, WorkCount& wc)
+{
+    // the ring's records were written by other lanes of this wavefront: its
+    // LDS accesses complete in issue order, so a wavefront fence (no wait on
+    // the global atomics in flight) orders them
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int lane = threadIdx.x;
+    const int ntake = count < kWave ? count : kWave;
+    if (lane < ntake) {
+        const int q = (head + lane) & (QCAP - 1);
+        const double z[4] = {Q.z[0][q], Q.z[1][q], Q.z[2][q], Q.z[3][q]};
+        const int w = Q.where[q];
+        const Tile& t = tiles[w & 0xFF];
+        spread_z<WORK>(z, Q.frac[q], t, Dbuf + (w >> 8), wc);
+    }
+    head = (head + ntake) & (QCAP - 1);
+    count -= ntake;
+}
+
+// Column (a,b) of one tile (valid lanes only; every lane of the wavefront
+// calls it): zeroes the D column, splits T by x <= a+1 and y <= b+1 as
+// column() does, and queues the pieces; full rounds of 64 are walked as they
+// fill.  Loops run to the wavefront's largest piece count, so that the
+// rounds are taken with every lane present.
+template <bool WORK, int QCAP>
+__device__ __forceinline__ void column_queue(bool valid, const CTet& S, int a, int b, const Tile& t,
+                                             int tile_idx, int doff, double* Dbuf,
+                                             PieceRing<QCAP>& Q, int& head, int& count,
+                                             const Tile* tiles, WorkCount& wc)
+{
+    const int lane = threadIdx.x;
+    int n1 = 0;
+    Split<double> s1;
+    double U0[2], U1[2], U2[2], W0[2], W1[2], W2[2];
+    if (valid) {
+        double* Dcol = Dbuf + doff;
+        for (int l = 0; l < t.tl; ++l) Dcol[l] = 0.0;
+        const bool cx = a + 1 < S.ext[0];
+        const double X = (double)(a + 1);
+        double v[4][3];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) v[q][c] = S.vr[q][c];
+        double dx[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dx[q] = cx ? X - v[q][0] : 1.0;
+        split_plane(dx, s1);
+        if (s1.nin > 0) {
+            double P1[4][2];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                P1[0][c] = sel4(v[0][c + 1], v[1][c + 1], v[2][c + 1], v[3][c + 1], s1.ia);
+                P1[1][c] = sel4(v[0][c + 1], v[1][c + 1], v[2][c + 1], v[3][c + 1], s1.ib);
+                P1[2][c] = sel4(v[0][c + 1], v[1][c + 1], v[2][c + 1], v[3][c + 1], s1.ic);
+                P1[3][c] = sel4(v[0][c + 1], v[1][c + 1], v[2][c + 1], v[3][c + 1], s1.id);
+            }
+            const bool a1 = s1.nin == 1, a2 = s1.nin == 2, a3 = s1.nin == 3, a4 = s1.nin == 4;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const double va = P1[0][c], vb = P1[1][c], vc = P1[2][c], vd = P1[3][c];
+                const double in1 = a3 ? vb : va, in2 = a1 ? va : (a2 ? vb : vc);
+                const double out0 = a1 ? vb : (a2 ? vc : vd), out1 = a1 ? vc : vd, out2 = a2 ? vc : vd;
+                const double c0 = va + s1.t0 * (out0 - va);
+                const double c1 = in1 + s1.t1 * (out1 - in1);
+                const double c2 = in2 + s1.t2 * (out2 - in2);
+                const double c3 = vb + s1.t3 * (vd - vb);
+                U0[c] = va;
+                U1[c] = (a3 || a4) ? vb : c0;
+                U2[c] = (a3 || a4) ? vc : c1;
+                W0[c] = a2 ? vb : c0;
+                W1[c] = a2 ? c2 : c1;
+                W2[c] = a4 ? vd : (a2 ? c3 : c2);
+            }
+            n1 = (a2 || a3) ? 3 : 1;
+            if constexpr (WORK) wc.xpiece += (unsigned long long)n1;
+        }
+    }
+    const int nj = __ballot(n1 == 3) ? 3 : (__ballot(n1 == 1) ? 1 : 0);
+    const bool cy = b + 1 < S.ext[1];
+    const double Y = (double)(b + 1);
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+    for (int j = 0; j < nj; ++j) {
+        int n2 = 0;
+        Split<double> s2;
+        double u0 = 0.0, u1 = 0.0, u2 = 0.0, w0 = 0.0, w1 = 0.0, w2 = 0.0, f1 = 0.0;
+        if (j < n1) {
+            double cv[4][2];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                cv[0][c] = U0[c];
+                cv[1][c] = j == 2 ? W0[c] : U1[c];
+                cv[2][c] = j == 0 ? U2[c] : W1[c];
+                cv[3][c] = W2[c];
+            }
+            f1 = j == 0 ? s1.f0 : (j == 1 ? s1.f1 : s1.f2);
+            double dy[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dy[q] = cy ? Y - cv[q][0] : 1.0;
+            split_plane(dy, s2);
+            if (s2.nin > 0) {
+                const double za = sel4(cv[0][1], cv[1][1], cv[2][1], cv[3][1], s2.ia);
+                const double zb = sel4(cv[0][1], cv[1][1], cv[2][1], cv[3][1], s2.ib);
+                const double zc = sel4(cv[0][1], cv[1][1], cv[2][1], cv[3][1], s2.ic);
+                const double zd = sel4(cv[0][1], cv[1][1], cv[2][1], cv[3][1], s2.id);
+                const bool b1 = s2.nin == 1, b2 = s2.nin == 2, b3 = s2.nin == 3, b4 = s2.nin == 4;
+                const double in1 = b3 ? zb : za, in2 = b1 ? za : (b2 ? zb : zc);
+                const double out0 = b1 ? zb : (b2 ? zc : zd), out1 = b1 ? zc : zd, out2 = b2 ? zc : zd;
+                const double c0 = za + s2.t0 * (out0 - za);
+                const double c1 = in1 + s2.t1 * (out1 - in1);
+                const double c2 = in2 + s2.t2 * (out2 - in2);
+                const double c3 = zb + s2.t3 * (zd - zb);
+                u0 = za;
+                u1 = (b3 || b4) ? zb : c0;
+                u2 = (b3 || b4) ? zc : c1;
+                w0 = b2 ? zb : c0;
+                w1 = b2 ? c2 : c1;
+                w2 = b4 ? zd : (b2 ? c3 : c2);
+                n2 = (b2 || b3) ? 3 : 1;
+                if constexpr (WORK) wc.piece += (unsigned long long)n2;
+            }
+        }
+        const int nk = __ballot(n2 == 3) ? 3 : (__ballot(n2 == 1) ? 1 : 0);
+        for (int k = 0; k < nk; ++k) {
+            const bool has = k < n2;
+            const uint64_t bal = __ballot(has);
+            if (has) {
+                const int q = (head + count + __popcll(bal & below)) & (QCAP - 1);
+                Q.z[0][q] = u0;
+                Q.z[1][q] = k == 2 ? w0 : u1;
+                Q.z[2][q] = k == 0 ? u2 : w1;
+                Q.z[3][q] = w2;
+                Q.frac[q] = f1 * (k == 0 ? s2.f0 : (k == 1 ? s2.f1 : s2.f2));
+                Q.where[q] = (doff << 8) | tile_idx;
+            }
+            count += __popcll(bal);
+            if (count >= kWave) drain_round<WORK, QCAP>(Q, head, count, tiles, Dbuf, wc);
+        }
+    }
+}
+
 // Index of the box holding global chunk g (boxes sorted by chunk_begin).
 __device__ __forceinline__ int box_of(const QueueArgs& Q, int64_t g)
 {
@@ -506,19 +667,24 @@ __device__ __forceinline__ void flush_mass(const BoxDesc& P, double& macc)
 // Three wavefronts per SIMD (12 per compute unit) need at most 13.6 KB of
 // LDS each and at most 168 registers (the launch bounds); the instances
 // trade slots for buffer: 32 tets set up at once with 960 entries and 16
-// tiles a batch suit small tetrahedra (many per batch), 8 tets with 1408
-// entries large ones (a few fill the buffer).  The 2048-entry instance runs
-// at two per SIMD.
-template <typename OutT, int CAP, int GROUP, int TILES, bool WORK>
+// tiles a batch suit small tetrahedra (many per batch), 8 tets with 1024
+// entries and a 128-piece ring (QCAP) large ones, whose columns are cut into
+// 1 to 9 pieces walking up to tens of levels each; 8 tets with 1408 entries
+// and no ring is the same walk with each column's pieces on its own lane.
+// The 2048-entry instance runs at two per SIMD.
+template <typename OutT, int CAP, int GROUP, int TILES, bool WORK, int QCAP>
 __global__ __launch_bounds__(kWave, (CAP <= 1408 ? 3 : 2)) void queue_kernel(QueueArgs Q)
 {
     static_assert(kWave % GROUP == 0 && GROUP <= kWave && TILES <= GROUP, "chunk of whole groups");
+    static_assert(QCAP == 0 || (QCAP >= 2 * kWave && (QCAP & (QCAP - 1)) == 0 && TILES <= 256 &&
+                                CAP < (1 << 23)), "piece ring: a power of two of at least 128");
     __shared__ CTet slots[GROUP];
     __shared__ double Dbuf[CAP];
     __shared__ Tile tiles[TILES];
     __shared__ int t_slot[TILES];
     __shared__ int64_t s_incl[TILES];
     __shared__ int64_t s_item;
+    __shared__ PieceRing<(QCAP > 0 ? QCAP : 1)> ring;
 
     const int lane = threadIdx.x;
     double macc = 0.0;
@@ -681,28 +847,61 @@ __global__ __launch_bounds__(kWave, (CAP <= 1408 ? 3 : 2)) void queue_kernel(Que
                 if (lane < TILES) s_incl[lane] = incl;  // nt <= TILES
                 __syncthreads();
                 const int64_t total = __shfl(incl, kWave - 1, kWave);
-                for (int64_t base = 0; base < total; base += kWave) {
-                    const int64_t idx = base + lane;
-                    int lo = 0, r = 0;
-                    if (idx < total) {
-                        int hi = nt - 1;
-                        while (lo < hi) {
-                            const int mid = (lo + hi) >> 1;
-                            if (s_incl[mid] > idx) hi = mid;
-                            else lo = mid + 1;
-                        }
+                // the tile of pair idx and its column's rank r within the tile
+                auto locate = [&](int64_t idx, int& lo, int& r) {
+                    lo = 0;
+                    int hi = nt - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_incl[mid] > idx) hi = mid;
+                        else lo = mid + 1;
+                    }
+                    r = (int)(idx - (s_incl[lo] - tile_cols(tiles[lo])));
+                };
+                if constexpr (QCAP > 0) {
+                    // Phase 1 for every window of the batch, the pieces of all
+                    // columns walked 64 at a time; phase 2 follows once the
+                    // ring is empty.
+                    int head = 0, count = 0;
+                    for (int64_t base = 0; base < total; base += kWave) {
+                        const int64_t idx = base + lane;
+                        const bool valid = idx < total;
+                        int lo = 0, r = 0;
+                        if (valid) locate(idx, lo, r);
                         const Tile t = tiles[lo];
                         const CTet& S = slots[t_slot[lo]];
-                        r = (int)(idx - (s_incl[lo] - tile_cols(t)));
                         const int wb = t.tb + t.hb;
                         const int qa = fdivi(r, t.inv_wb);
                         const int a = t.a0 - t.ha + qa;
                         const int b = t.b0 - t.hb + (r - qa * wb);
-                        column<WORK>(S, a, b, t, Dbuf + t.doff + r * t.tl, wc);
-                        ++n_col;
-                        if constexpr (WORK) n_colcell += (unsigned long long)t.tl;
+                        column_queue<WORK, QCAP>(valid, S, a, b, t, lo, t.doff + r * t.tl, Dbuf,
+                                                 ring, head, count, tiles, wc);
+                        if (valid) {
+                            ++n_col;
+                            if constexpr (WORK) n_colcell += (unsigned long long)t.tl;
+                        }
                     }
+                    while (count > 0) drain_round<WORK, QCAP>(ring, head, count, tiles, Dbuf, wc);
                     __syncthreads();
+                }
+                for (int64_t base = 0; base < total; base += kWave) {
+                    const int64_t idx = base + lane;
+                    int lo = 0, r = 0;
+                    if (idx < total) locate(idx, lo, r);
+                    if constexpr (QCAP == 0) {
+                        if (idx < total) {
+                            const Tile t = tiles[lo];
+                            const CTet& S = slots[t_slot[lo]];
+                            const int wb = t.tb + t.hb;
+                            const int qa = fdivi(r, t.inv_wb);
+                            const int a = t.a0 - t.ha + qa;
+                            const int b = t.b0 - t.hb + (r - qa * wb);
+                            column<WORK>(S, a, b, t, Dbuf + t.doff + r * t.tl, wc);
+                            ++n_col;
+                            if constexpr (WORK) n_colcell += (unsigned long long)t.tl;
+                        }
+                        __syncthreads();
+                    }
                     // Phase 2: the cells (i, j, l) of this lane's column, l
                     // walking the tile's levels; halo columns have no cells.
                     if (idx < total) {
@@ -962,23 +1161,18 @@ QueueLayout queue_layout(int64_t n_chunks, int n_boxes, bool ordered)
 template <typename OutT, bool WORK>
 const void* queue_kernel_for(int cap)
 {
-    if (cap <= 512) return reinterpret_cast<const void*>(&queue_kernel<OutT, 512, 16, 16, WORK>);
-    if (cap <= 960) return reinterpret_cast<const void*>(&queue_kernel<OutT, 960, 32, 16, WORK>);
-    if (cap <= 1408) return reinterpret_cast<const void*>(&queue_kernel<OutT, 1408, 8, 8, WORK>);
-    return reinterpret_cast<const void*>(&queue_kernel<OutT, 2048, 32, 32, WORK>);
+    if (cap <= 512) return reinterpret_cast<const void*>(&queue_kernel<OutT, 512, 16, 16, WORK, 0>);
+    if (cap <= 960) return reinterpret_cast<const void*>(&queue_kernel<OutT, 960, 32, 16, WORK, 0>);
+    if (cap <= 1024) return reinterpret_cast<const void*>(&queue_kernel<OutT, 1024, 8, 8, WORK, 128>);
+    if (cap <= 1408) return reinterpret_cast<const void*>(&queue_kernel<OutT, 1408, 8, 8, WORK, 0>);
+    return reinterpret_cast<const void*>(&queue_kernel<OutT, 2048, 32, 32, WORK, 0>);
 }
 
 template <typename OutT, bool WORK>
 hipError_t launch_queue_kernel(const QueueArgs& Q, int cap, int grid, hipStream_t stream)
 {
-    if (cap <= 512)
-        hipLaunchKernelGGL((queue_kernel<OutT, 512, 16, 16, WORK>), dim3(grid), dim3(kWave), 0, stream, Q);
-    else if (cap <= 960)
-        hipLaunchKernelGGL((queue_kernel<OutT, 960, 32, 16, WORK>), dim3(grid), dim3(kWave), 0, stream, Q);
-    else if (cap <= 1408)
-        hipLaunchKernelGGL((queue_kernel<OutT, 1408, 8, 8, WORK>), dim3(grid), dim3(kWave), 0, stream, Q);
-    else
-        hipLaunchKernelGGL((queue_kernel<OutT, 2048, 32, 32, WORK>), dim3(grid), dim3(kWave), 0, stream, Q);
+    hipLaunchKernelGGL(reinterpret_cast<void (*)(QueueArgs)>(const_cast<void*>(queue_kernel_for<OutT, WORK>(cap))),
+                       dim3(grid), dim3(kWave), 0, stream, Q);
     return hipGetLastError();
 }
 
@@ -1005,15 +1199,16 @@ int auto_cap(const BoxDesc* boxes, int n_boxes)
         for (int a = 0; a < 3; ++a)
             ratio = fmin(ratio, (double)boxes[b].nc[a] / (double)boxes[b].np[a]);
     }
-    return ratio >= 1.5 ? 1408 : 960;
+    return ratio >= 1.5 ? 1024 : 960;
 }
 
 hipError_t queue_resident_waves(int cap, bool out_fp64, int& waves, bool work)
 {
     // one kernel instance per (buffer size, output type, counters); the
     // answer only depends on the instance, so it is asked once
-    static std::atomic<int> known[4][2][2];
-    const int ci = cap <= 512 ? 0 : (cap <= 960 ? 1 : (cap <= 1408 ? 2 : 3)), ti = out_fp64 ? 1 : 0;
+    static std::atomic<int> known[5][2][2];
+    const int ci = cap <= 512 ? 0 : (cap <= 960 ? 1 : (cap <= 1024 ? 2 : (cap <= 1408 ? 3 : 4)));
+    const int ti = out_fp64 ? 1 : 0;
     const int wi = work ? 1 : 0;
     int n = known[ci][ti][wi].load(std::memory_order_relaxed);
     if (n == 0) {

@@ -9,7 +9,8 @@
 // HBM-bound: 8 B of ID and 12 B of position read and 12 B written per record,
 // reads coalesced, writes wherever the IDs send them.  With the optional check
 // a one-bit-per-slot occupancy map (an atomic OR per record) finds duplicate
-// IDs, and a popcount pass finds the slots no record names.
+// IDs -- only the record that claims a slot first writes it -- and a popcount
+// pass finds the slots no record names.
 #include "psd_internal.h"
 
 namespace psd {
@@ -40,16 +41,21 @@ __global__ __launch_bounds__(kIngestBlock) void scatter_by_id_kernel(
             ++bad;
             continue;
         }
+        if (CHECK) {
+            // the record that sets the slot's bit first is the one stored, whole;
+            // later records naming the slot are only counted
+            const unsigned bit = 1u << (unsigned)(slot & 31);
+            const unsigned old = atomicOr(occupied + (slot >> 5), bit);
+            if (old & bit) {
+                ++dup;
+                continue;
+            }
+        }
         const float x = pos_in[3 * r + 0], y = pos_in[3 * r + 1], z = pos_in[3 * r + 2];
         float* o = pos_out + 3 * slot;
         o[0] = x;
         o[1] = y;
         o[2] = z;
-        if (CHECK) {
-            const unsigned bit = 1u << (unsigned)(slot & 31);
-            const unsigned old = atomicOr(occupied + (slot >> 5), bit);
-            dup += (old & bit) ? 1 : 0;
-        }
     }
     if (CHECK) {
         bad = wave_sum(bad);

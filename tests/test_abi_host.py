@@ -102,9 +102,9 @@ def test_deposit_rejects_bad_arguments_before_launch(psd):
 def test_launch_shape_validation(psd):
     # buffer sizes are the kernel's instances; 0 means the defaults (chosen from
     # the grid's cells per spacing, as many wavefronts as fit a compute unit)
-    for cap in (0, 512, 960, 1408, 2048):
+    for cap in (0, 512, 960, 1024, 1408, 2048):
         assert psd.uniform_workspace_size((8, 8, 8), 16, tuning=(cap, 0, 0)) > 0
-    for bad in ((1024, 0, 0), (960, -1, 0), (960, 65, 0)):
+    for bad in ((1000, 0, 0), (960, -1, 0), (960, 65, 0)):
         with pytest.raises(psd.PsdError) as e:
             psd.uniform_workspace_size((8, 8, 8), 16, tuning=bad)
         assert e.value.code == psd.PSD_ERR_ARG

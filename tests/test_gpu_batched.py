@@ -37,7 +37,7 @@ def _small_batch():
 
 
 @pytest.mark.parametrize("tuning", [None, (512, 4, 0), (2048, 8, 1), (960, 2, 1), (960, 12, 0),
-                                    (1408, 12, 1)])
+                                    (1408, 12, 1), (1024, 12, 0), (1024, 5, 1)])
 def test_batch_equals_single_boxes_and_oracle(psd, orc, tuning):
     dev = torch.device("cuda:0")
     batch = _small_batch()
@@ -76,7 +76,7 @@ def test_autotuner_picks_a_valid_shape_and_caches(psd, tmp_path):
     tens = [(torch.from_numpy(p).to(dev), nc) for p, nc in _small_batch()]
     cache = str(tmp_path / "tune.json")
     (cap, waves, ordered), ms = psd.autotune_batched(tens, cache_path=cache)
-    assert cap in (960, 1408, 2048) and 1 <= waves <= 64 and ordered in (0, 1) and ms > 0
+    assert cap in (960, 1024, 2048) and 1 <= waves <= 64 and ordered in (0, 1) and ms > 0
     data = json.load(open(cache))
     assert len(data) == 1
     again, ms2 = psd.autotune_batched(tens, cache_path=cache)

@@ -89,7 +89,8 @@ def test_leaf_deposit_matches_oracle(psd, orc, case):
                        atol=1e-12)
 
 
-@pytest.mark.parametrize("tuning", [(960, 12, 1), (512, 4, 0), (2048, 7, 0), (1408, 12, 0)])
+@pytest.mark.parametrize("tuning", [(960, 12, 1), (512, 4, 0), (2048, 7, 0), (1408, 12, 0),
+                                    (1024, 12, 0)])
 def test_leaf_deposit_launch_shapes_agree(psd, orc, tuning):
     """Cost order (no skipping of leafless levels) and other LDS buffers give the same
     leaves; the tree here has leaves at several levels and leafless ones above them."""

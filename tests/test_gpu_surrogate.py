@@ -4,8 +4,9 @@
   exact fractions within 1e-10 (both FP64, different clippers);
 - forward / backward: the network on the GPU (BF16 matrix cores, FP32
   accumulate, BF16 activations between layers) against the FP64 reference on
-  the same BF16-rounded weights: relative norm <= 2e-2 (a few BF16 roundings
-  of 2^-9 per layer, amplified through three layers);
+  the same BF16-rounded weights: relative norm <= 1e-2, for the whole output
+  and for every parameter block (measured: forward 4e-5, or 2e-3 with
+  weights three times larger; gradient 6e-5, blocks below 3e-4);
 - Adam: FP32 update against the FP64 reference, relative 1e-5;
 - deposit: the surrogate deposit equals the oracle's composition (exact for
   the other tetrahedra, the FP64 reference network for the eligible ones),
@@ -26,7 +27,7 @@ from synth import TRAIN_SEED0, uniform_segments, workload, zeldovich_positions
 
 pytestmark = pytest.mark.gpu
 
-NET_TOL = 2e-2
+NET_TOL = 1e-2
 
 
 @pytest.fixture(scope="module")
@@ -124,6 +125,8 @@ def test_forward_matches_reference(psd, orc, scale):
     mb = S.mask_bits(m)
     assert np.all(got[~mb] == 0.0)
     assert np.allclose(got.sum(1), 1.0, atol=1e-6)
+    print(f"forward scale {scale}: relative norm {_rel(got, ref):.3e}, "
+          f"max |dp| {np.abs(got - ref).max():.3e}", flush=True)
     assert _rel(got, ref) <= NET_TOL, _rel(got, ref)
 
 
@@ -136,13 +139,16 @@ def test_backward_matches_reference(psd, orc):
                                      idx=_dev(idx))
     L, gref = S.backward(S.effective(w), ex["feat"][idx], ex["frac"][idx], ex["mask"][idx])
     g = g.cpu().numpy()
+    print(f"backward: loss rel {abs(float(loss.item()) - L) / abs(L):.3e}, "
+          f"gradient relative norm {_rel(g, gref):.3e}", flush=True)
     assert float(loss.item()) == pytest.approx(L, rel=5e-3)
     assert _rel(g, gref) <= NET_TOL, _rel(g, gref)
     # every parameter block on its own
     o = 0
     for name, shape in S.LAYOUT:
         k = int(np.prod(shape))
-        assert _rel(g[o:o + k], gref[o:o + k]) <= 3 * NET_TOL, (name, _rel(g[o:o + k], gref[o:o + k]))
+        print(f"  {name}: {_rel(g[o:o + k], gref[o:o + k]):.3e}", flush=True)
+        assert _rel(g[o:o + k], gref[o:o + k]) <= NET_TOL, (name, _rel(g[o:o + k], gref[o:o + k]))
         o += k
 
 

@@ -148,7 +148,8 @@ def _max_bbox_cells(orc, pos, nc):
     return best
 
 
-@pytest.mark.parametrize("tuning", [(512, 0, 0), (960, 0, 1), (1408, 0, 0), (2048, 0, 0)])
+@pytest.mark.parametrize("tuning", [(512, 0, 0), (960, 0, 1), (1024, 0, 0), (1408, 0, 0),
+                                    (2048, 0, 0)])
 def test_huge_tets_tiled_in_every_instance(psd, orc, tuning):
     # tets of thousands of bbox cells are tiled with halo columns; in the 16-tet
     # instances they also interrupt the all-lanes planning of untiled runs
@@ -260,14 +261,15 @@ def test_zel256_g512_sampled_blocks(psd, orc, method):
 
 @pytest.mark.parametrize("nc", [64, 20])
 def test_kernel_instances_agree(psd, orc, nc):
-    # 32^3 particles onto 64^3 (2 cells per spacing: the default is the 1408-entry
+    # 32^3 particles onto 64^3 (2 cells per spacing: the default is the 1024-entry
     # buffer with 8-tet groups) and onto 20^3 (0.6: 960 entries, 16-tet groups);
     # every instance and launch shape gives the oracle's grid in FP64
     pos = zeldovich_positions(32, 0.5, seed=9)
     ref, _ = orc.deposit_uniform(pos, nc)
     dev = torch.device("cuda:0")
     pt = torch.from_numpy(pos).to(dev)
-    for tuning in (None, (512, 0, 0), (960, 12, 1), (1408, 12, 0), (2048, 7, 0), (1408, 3, 1)):
+    for tuning in (None, (512, 0, 0), (960, 12, 1), (1024, 12, 0), (1024, 4, 1), (1408, 12, 0),
+                   (2048, 7, 0), (1408, 3, 1)):
         ms = torch.zeros(1, dtype=torch.float64, device=dev)
         out = psd.deposit_uniform(pt, nc, flags=psd.PSD_PREC_FP64, mass_sum=ms, tuning=tuning)
         got = out.cpu().numpy()
@@ -275,7 +277,7 @@ def test_kernel_instances_agree(psd, orc, nc):
         assert abs(float(ms.item()) - 1.0) <= 1e-12
 
 
-@pytest.mark.parametrize("cap", [1408, 960])
+@pytest.mark.parametrize("cap", [1024, 1408, 960])
 def test_work_counters_match_cost_model(psd, orc, cap):
     """The instrumented kernel's work events (PSD_WORK_COUNTERS) equal the CPU replay of
     the cumulative walk in costmodel.py on every tetrahedron of 32^3 -> 64^3; the split
