@@ -183,7 +183,8 @@ def atomic_peaks(torch) -> dict:
     buf = torch.zeros(words, dtype=torch.float32, device=dev)
     blocks = 256 * 16
     out = {}
-    for name, pat in (("global_atomic_add_f32_coalesced", 0), ("global_atomic_add_f32_random", 1)):
+    for name, pat in (("global_atomic_add_f32_coalesced", 0), ("global_atomic_add_f32_random", 1),
+                      ("global_atomic_add_f32_column_walks", 2)):
         def run(pat=pat):
             n = L.peaks_global_atomic_f32(buf.data_ptr(), words, blocks, 64, pat, sh)
             if n < 0:
@@ -426,10 +427,12 @@ def roofline_line(kernel: str, kernel_ms: float, ntet: int, own: dict | None,
             "equivalent_frac": paper_ops * ntet / t / PEAK_VALU_OPS,
             "note": "the paper's per-cell splitting priced with its frozen unit costs: the "
                     "work that method would do at this speed, not a fraction of a roofline"}
-    if n_atomic is not None and peaks and "global_atomic_add_f32_random" in peaks:
-        pa = peaks["global_atomic_add_f32_random"]
+    if n_atomic is not None and peaks and "global_atomic_add_f32_column_walks" in peaks:
+        # the deposit's scatter: each lane walks its column's levels along one axis
+        pa = peaks["global_atomic_add_f32_column_walks"]
         terms["atomic_s"] = n_atomic / pa
-        line["atomic"] = {"n_atomic": n_atomic, "peak_random": pa,
+        line["atomic"] = {"n_atomic": n_atomic, "peak_column_walks": pa,
+                          "peak_random": peaks.get("global_atomic_add_f32_random"),
                           "peak_coalesced": peaks.get("global_atomic_add_f32_coalesced"),
                           "achieved": n_atomic / t, "frac": n_atomic / t / pa,
                           "unit": "atomics/s"}

@@ -9,8 +9,13 @@
 //     (global_atomic_add_f32 without return), the scatter of the deposit's
 //     phase 2.  pattern 0: lanes of a wavefront hit consecutive words
 //     (coalesced); pattern 1: every add goes to a hashed word of the array
-//     (random).  n is a power of two and addresses are masked to n - 1, so
-//     every access is in bounds.
+//     (random); pattern 2: every lane walks runs of 8 consecutive cells along
+//     one axis of a 512^3 grid from a hashed start, the axis (stride 1, 512
+//     or 512^2 words) the same across a wavefront and changing from one
+//     wavefront to the next -- the deposit's phase 2, where each lane walks
+//     the levels of its own column along the tetrahedron's walk axis.  n is a
+//     power of two and addresses are masked to n - 1, so every access is in
+//     bounds.
 //   peaks_lds_atomic: LDS atomic adds without return (ds_add_f32 or
 //     ds_add_f64, the deposit's level increments) to lane-consecutive words
 //     of a 2048-word array per workgroup, bank-conflict free.
@@ -39,8 +44,16 @@ __global__ __launch_bounds__(kBlock) void global_atomic_kernel(float* __restrict
     const uint32_t nthreads = gridDim.x * kBlock;
     for (int i = 0; i < iters; ++i) {
         uint32_t a;
-        if (pattern == 0) a = ((uint32_t)i * nthreads + tid) & mask;
-        else a = mix32(tid * 0x9e3779b9u + (uint32_t)i * 0x85ebca6bu) & mask;
+        if (pattern == 0) {
+            a = ((uint32_t)i * nthreads + tid) & mask;
+        } else if (pattern == 1) {
+            a = mix32(tid * 0x9e3779b9u + (uint32_t)i * 0x85ebca6bu) & mask;
+        } else {
+            const uint32_t wave = tid >> 6;
+            const uint32_t stride = (wave % 3u) == 0u ? 1u : ((wave % 3u) == 1u ? 512u : 512u * 512u);
+            const uint32_t start = mix32(tid * 0x9e3779b9u + (uint32_t)(i >> 3) * 0x85ebca6bu);
+            a = (start + (uint32_t)(i & 7) * stride) & mask;
+        }
         __hip_atomic_fetch_add(buf + a, 1.0f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
@@ -75,7 +88,7 @@ int64_t peaks_global_atomic_f32(float* buf, int64_t n, int blocks, int iters, in
                                 void* stream)
 {
     if (!buf || n < 1 || n > (1ll << 31) || (n & (n - 1)) != 0 || blocks < 1 || iters < 1 ||
-        (pattern != 0 && pattern != 1))
+        pattern < 0 || pattern > 2)
         return -1;
     hipLaunchKernelGGL(global_atomic_kernel, dim3(blocks), dim3(kBlock), 0,
                        reinterpret_cast<hipStream_t>(stream), buf, (uint32_t)(n - 1), iters, pattern);
