@@ -746,11 +746,16 @@ def main() -> int:
     print("FP64 grid, per-cell method, surrogate ...", file=sys.stderr, flush=True)
     # the same deposit into an FP64 grid (identical arithmetic, double atomics)
     ms64, _ = time_deposit(psd, torch, pt, nc, psd.PSD_PREC_FP64, reps=max(1, min(args.steps, 2)))
-    # the per-cell method: cell-local FP32 clipping (one timed run)
+    # the per-cell method: cell-local FP32 clipping (one timed run), and the cached slab
+    # clipping in FP32 beside it at the same error
     ms_cell, cell_grid = (None, None)
+    ms_slab, slab_grid = (None, None)
     if not args.no_cell:
         ms_cell, g = time_deposit(psd, torch, pt, nc, psd.PSD_METHOD_CELL, reps=1)
         cell_grid = g.double().cpu().numpy()
+        del g
+        ms_slab, g = time_deposit(psd, torch, pt, nc, psd.PSD_METHOD_SLAB, reps=2)
+        slab_grid = g.double().cpu().numpy()
         del g
 
     sur = None
@@ -779,7 +784,8 @@ def main() -> int:
     if not args.no_cpu:
         print("oracle on the host ...", file=sys.stderr, flush=True)
         cpu = cpu_baseline(pos, nc, grid, args.cpu_cubes,
-                           other_grids={"fp32_cell_local": cell_grid} if cell_grid is not None else None,
+                           other_grids=({"fp32_cell_local": cell_grid, "fp32_slab": slab_grid}
+                                        if cell_grid is not None else None),
                            single_thread_cubes=10_000)
         pcnt = cpu.pop("_paper_counters")
         cnt = cpu.pop("_counters")
@@ -824,6 +830,10 @@ def main() -> int:
         "fp32_cell_local": ({"tets_per_s": ntet / (ms_cell / 1e3), "ms": ms_cell,
                              "block_l1": (cpu or {}).get("fp32_cell_local_block_l1")}
                             if ms_cell else None),
+        "fp32_slab": ({"tets_per_s": ntet / (ms_slab / 1e3), "ms": ms_slab,
+                       "block_l1": (cpu or {}).get("fp32_slab_block_l1"),
+                       "speedup_vs_cell_local": ms_cell / ms_slab}
+                      if ms_slab else None),
     }
     if cpu is not None and "gpu_block_l1" in cpu:
         line["density_l1_sampled_block"] = cpu["gpu_block_l1"]

@@ -73,7 +73,7 @@ enum {
                                   nothing else enqueued and the outputs
                                   untouched) if one is NaN or infinite.  The
                                   call then synchronizes `stream`.            */
-    PSD_WORK_COUNTERS = 1u << 6 /* with stats: stats holds 16 entries and the
+    PSD_WORK_COUNTERS = 1u << 6, /* with stats: stats holds 16 entries and the
                                   default (cumulative) method runs an
                                   instrumented kernel that also adds its work
                                   events into [8] pieces of the first split,
@@ -82,6 +82,21 @@ enum {
                                   by those pieces, [11] (column, level) slots
                                   of the walked tiles; [12..15] reserved.  For
                                   measurement: the plain kernel is faster.    */
+    PSD_METHOD_SLAB = 1u << 7   /* cached slab clipping in FP32 (Section 6.3's
+                                  splitting, each split computed once where
+                                  its pieces serve many cells): per bbox row
+                                  x in [a, a+1) the pieces of T cut by
+                                  x >= a and x <= a+1 (FP64 planes, kept in
+                                  FP32 relative to the tile), per column the
+                                  row's pieces cut by y >= b and y <= b+1 in
+                                  FP32, and the leaves' exact z distribution
+                                  summed into the column's cells.  Cell
+                                  volumes are formed directly (no differences
+                                  of cumulative values), so FP32 keeps its
+                                  relative precision in every cell.  FP32
+                                  grids only; not with PSD_PREC_FP64,
+                                  PSD_METHOD_CELL, PSD_SURROGATE or
+                                  PSD_WORK_COUNTERS.                          */
 };
 
 typedef struct {

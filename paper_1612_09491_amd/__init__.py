@@ -32,6 +32,7 @@ PSD_METHOD_CELL = 1 << 3
 PSD_SURROGATE = 1 << 4
 PSD_CHECK_FINITE = 1 << 5
 PSD_WORK_COUNTERS = 1 << 6
+PSD_METHOD_SLAB = 1 << 7
 
 PSD_SURROGATE_PARAMS = 9672
 

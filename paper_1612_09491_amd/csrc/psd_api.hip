@@ -61,6 +61,7 @@ psd::Tuning tuning_from(const psd_options* opt)
         t.ordered = u->ordered ? 1 : 0;
     }
     if (opt && (opt->flags & PSD_WORK_COUNTERS) && opt->stats) t.work_counters = 1;
+    if (opt && (opt->flags & PSD_METHOD_SLAB)) t.slab = 1;
     return t;
 }
 
@@ -121,7 +122,14 @@ psd::OctreeArgs octree_args(const float* pos, const psd_particles* p, const psd_
 }
 constexpr uint32_t kUniformFlags = PSD_OUT_DENSITY | PSD_ACCUMULATE | PSD_PREC_FP64 |
                                    PSD_METHOD_CELL | PSD_SURROGATE | PSD_CHECK_FINITE |
-                                   PSD_WORK_COUNTERS;
+                                   PSD_WORK_COUNTERS | PSD_METHOD_SLAB;
+
+// The slab form writes FP32 grids and has no surrogate or counting variant.
+bool slab_flags_ok(uint32_t flags)
+{
+    return !(flags & PSD_METHOD_SLAB) ||
+           !(flags & (PSD_PREC_FP64 | PSD_METHOD_CELL | PSD_SURROGATE | PSD_WORK_COUNTERS));
+}
 
 // PSD_ERR_NONFINITE when one of the n particles' coordinates is NaN or
 // infinite; the device word `scratch` (inside the caller's workspace) holds
@@ -178,6 +186,9 @@ psd_status psd_uniform_workspace_size(const psd_particles* p, const int32_t nc[3
     if (!particles_ok(p)) return fail(PSD_ERR_ARG, "bad particle description");
     if (!grid_ok(nc)) return fail(PSD_ERR_ARG, "bad grid size");
     if (opt && (opt->flags & ~kUniformFlags)) return fail(PSD_ERR_UNSUPPORTED, "unknown flags");
+    if (opt && !slab_flags_ok(opt->flags))
+        return fail(PSD_ERR_UNSUPPORTED, "PSD_METHOD_SLAB writes FP32 grids, without the surrogate, "
+                                         "PSD_METHOD_CELL or PSD_WORK_COUNTERS");
     if (opt && (opt->flags & PSD_METHOD_CELL) && !cell_method_fits(nc))
         return fail(PSD_ERR_UNSUPPORTED, "PSD_METHOD_CELL needs (nc0+1)(nc1+1)(nc2+1) < 2^31");
     if (!tuning_ok(opt)) return fail(PSD_ERR_ARG, "bad tuning");
@@ -194,6 +205,9 @@ psd_status psd_deposit_uniform(const float* pos, const psd_particles* p, const i
     if (!grid_ok(nc)) return fail(PSD_ERR_ARG, "bad grid size");
     const uint32_t flags = opt ? opt->flags : 0u;
     if (flags & ~kUniformFlags) return fail(PSD_ERR_UNSUPPORTED, "unknown flags");
+    if (!slab_flags_ok(flags))
+        return fail(PSD_ERR_UNSUPPORTED, "PSD_METHOD_SLAB writes FP32 grids, without the surrogate, "
+                                         "PSD_METHOD_CELL or PSD_WORK_COUNTERS");
     if ((flags & PSD_METHOD_CELL) && !cell_method_fits(nc))
         return fail(PSD_ERR_UNSUPPORTED, "PSD_METHOD_CELL needs (nc0+1)(nc1+1)(nc2+1) < 2^31");
     if (!tuning_ok(opt)) return fail(PSD_ERR_ARG, "bad tuning");

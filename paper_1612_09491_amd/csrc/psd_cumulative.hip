@@ -26,6 +26,7 @@
 #include <string.h>
 
 #include <atomic>
+#include <type_traits>
 #include <vector>
 
 #include "psd_internal.h"
@@ -74,6 +75,18 @@ __device__ __forceinline__ void tile_shape(const CTet& S, int& ta, int& tb, int&
     tl = min(S.ext[2], CAP / 4);
     tb = min(S.ext[1], CAP / (2 * tl) - 1);
     ta = min(S.ext[0], CAP / (tl * (tb + 1)) - 1);
+    ntiles = ((S.ext[0] + ta - 1) / ta) * ((S.ext[1] + tb - 1) / tb) * ((S.ext[2] + tl - 1) / tl);
+}
+
+// The slab form's tiles (no halo columns, at most `rows` tile rows):
+// ta*tb*tl <= CAP.
+template <int CAP>
+__device__ __forceinline__ void tile_shape_slab(const CTet& S, int rows, int& ta, int& tb, int& tl,
+                                                int& ntiles)
+{
+    tl = min(S.ext[2], CAP / 4);
+    tb = min(S.ext[1], CAP / (2 * tl));
+    ta = min(min(S.ext[0], rows), CAP / (tl * tb));
     ntiles = ((S.ext[0] + ta - 1) / ta) * ((S.ext[1] + tb - 1) / tb) * ((S.ext[2] + tl - 1) / tl);
 }
 
@@ -130,54 +143,67 @@ __device__ __forceinline__ bool touches_leaf(const BoxDesc& P, const int lo[3], 
 // (the inside-part fractions of a plane split, Section 6.3's table, for a
 // plane parallel to the cell faces; every term is a product of factors in
 // [0, 1], so nothing cancels).
+// R is the arithmetic type: double in the cumulative walk (its differences
+// cancel), float in the slab form (cell volumes summed directly).
+template <typename R>
 struct ZDist {
-    double s0, s1, s2, s3;
-    double iA, iC;            // reciprocal products of the two end regions
-    double r20, r30, r21, r31;
+    R s0, s1, s2, s3;
+    R iA, iC;            // reciprocal products of the two end regions
+    R r20, r30, r21, r31;
 };
 
+// 1/d for d > 0, else 0: the FP64 estimate refined by one Newton step, or the
+// FP32 hardware reciprocal (1 ulp).
 __device__ __forceinline__ double rcp_or0(double d)
 {
     double r = __builtin_amdgcn_rcp(d);
     r = fma(fma(-d, r, 1.0), r, r);
     return d > 0.0 ? r : 0.0;
 }
-
-__device__ __forceinline__ void zdist_init(const double z[4], ZDist& Z)
+__device__ __forceinline__ float rcp_or0(float d)
 {
-    double a = fmin(z[0], z[1]), b = fmax(z[0], z[1]);
-    double c = fmin(z[2], z[3]), d = fmax(z[2], z[3]);
-    const double s0 = fmin(a, c), t1 = fmax(a, c);
-    const double s3 = fmax(b, d), t2 = fmin(b, d);
+    const float r = __builtin_amdgcn_rcpf(d);
+    return d > 0.0f ? r : 0.0f;
+}
+
+template <typename R>
+__device__ __forceinline__ void zdist_init(const R z[4], ZDist<R>& Z)
+{
+    R a = fmin(z[0], z[1]), b = fmax(z[0], z[1]);
+    R c = fmin(z[2], z[3]), d = fmax(z[2], z[3]);
+    const R s0 = fmin(a, c), t1 = fmax(a, c);
+    const R s3 = fmax(b, d), t2 = fmin(b, d);
     Z.s0 = s0;
     Z.s1 = fmin(t1, t2);
     Z.s2 = fmax(t1, t2);
     Z.s3 = s3;
-    const double d10 = Z.s1 - s0, d20 = Z.s2 - s0, d30 = s3 - s0;
-    const double d21 = Z.s2 - Z.s1, d31 = s3 - Z.s1, d32 = s3 - Z.s2;
+    const R d10 = Z.s1 - s0, d20 = Z.s2 - s0, d30 = s3 - s0;
+    const R d21 = Z.s2 - Z.s1, d31 = s3 - Z.s1, d32 = s3 - Z.s2;
     // the middle region's four reciprocals from one: all four differences
     // are positive whenever that region is not empty (else they are unused)
-    const double P1 = d20 * d30, P2 = d21 * d31;
-    const double R = rcp_or0(P1 * P2);
-    Z.r20 = d30 * P2 * R;
-    Z.r30 = d20 * P2 * R;
-    Z.r21 = P1 * d31 * R;
-    Z.r31 = P1 * d21 * R;
+    const R P1 = d20 * d30, P2 = d21 * d31;
+    const R Rp = rcp_or0(P1 * P2);
+    Z.r20 = d30 * P2 * Rp;
+    Z.r30 = d20 * P2 * Rp;
+    Z.r21 = P1 * d31 * Rp;
+    Z.r31 = P1 * d21 * Rp;
     Z.iA = rcp_or0(d10 * d20 * d30);
     Z.iC = rcp_or0(d30 * d31 * d32);
 }
 
-__device__ __forceinline__ double zdist_below(const ZDist& Z, double k)
+template <typename R>
+__device__ __forceinline__ R zdist_below(const ZDist<R>& Z, R k)
 {
-    const double u = k - Z.s0, w = Z.s3 - k, t = k - Z.s1;
-    const double lowr = u * u * u * Z.iA;
-    const double highr = 1.0 - w * w * w * Z.iC;
-    const double t02 = u * Z.r20, t03 = u * Z.r30;
-    const double t12 = t * Z.r21, t13 = t * Z.r31;
-    const double mid = t02 * t03 * (1.0 - t13) + t02 * (1.0 - t12) * t13 + t12 * t13;
-    double F = k <= Z.s1 ? lowr : (k >= Z.s2 ? highr : mid);
-    F = k >= Z.s3 ? 1.0 : F;
-    return k <= Z.s0 ? 0.0 : F;
+    const R one = R(1);
+    const R u = k - Z.s0, w = Z.s3 - k, t = k - Z.s1;
+    const R lowr = u * u * u * Z.iA;
+    const R highr = one - w * w * w * Z.iC;
+    const R t02 = u * Z.r20, t03 = u * Z.r30;
+    const R t12 = t * Z.r21, t13 = t * Z.r31;
+    const R mid = t02 * t03 * (one - t13) + t02 * (one - t12) * t13 + t12 * t13;
+    R F = k <= Z.s1 ? lowr : (k >= Z.s2 ? highr : mid);
+    F = k >= Z.s3 ? one : F;
+    return k <= Z.s0 ? R(0) : F;
 }
 
 // Work events of the cumulative walk, counted only by the instrumented
@@ -190,7 +216,8 @@ struct WorkCount {
 
 // LDS add with no returned value (one ds_add_f64): the lane does not wait for
 // the old value, as a read-modify-write of its own column would.
-__device__ __forceinline__ void lds_add(double* p, double v)
+template <typename R>
+__device__ __forceinline__ void lds_add(R* p, R v)
 {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -204,77 +231,77 @@ __device__ __forceinline__ void lds_add(double* p, double v)
 // step, a quadratic evaluated directly (nothing is carried from level to
 // level, so no error accumulates); the end regions' quadratics have only
 // positive terms.
-template <bool WORK>
-__device__ __forceinline__ void spread_z(const double z[4], double frac, const Tile& t,
-                                         double* Dcol, WorkCount& wc)
+template <bool WORK, typename R>
+__device__ __forceinline__ void spread_z(const R z[4], R frac, const Tile& t, R* Dcol,
+                                         WorkCount& wc)
 {
-    ZDist Z;
+    ZDist<R> Z;
     zdist_init(z, Z);
     const int lfirst = (int)floor(Z.s0);
     const int lA = max(lfirst, t.l0);
     const int lB = min((int)floor(Z.s3), t.l0 + t.tl - 1);
     if (lA > lB) return;
     if constexpr (WORK) wc.level += (unsigned long long)(lB - lA + 1);
-    double Fprev = (lA <= lfirst) ? 0.0 : frac * zdist_below(Z, (double)lA);
-    double* p = Dcol + (lA - t.l0);
-    double k = (double)(lA + 1);       // upper plane of the level
-    const double kB = (double)(lB + 1);
+    R Fprev = (lA <= lfirst) ? R(0) : frac * zdist_below(Z, (R)lA);
+    R* p = Dcol + (lA - t.l0);
+    R k = (R)(lA + 1);       // upper plane of the level
+    const R kB = (R)(lB + 1);
     // Each region: its first level from F at both planes (the lower plane
     // may lie in the region before), the others from the difference of the
     // region's cubic over a unit step, a quadratic in the upper plane.
     // k <= s1: F = fA u^3, u = k - s0; step fA (3u^2 - 3u + 1), u >= 1
-    const double fA = frac * Z.iA;
-    const double kLow = fmin(Z.s1, kB);
+    const R fA = frac * Z.iA;
+    const R kLow = fmin(Z.s1, kB);
     if (k <= kLow) {
-        double u = k - Z.s0;
+        R u = k - Z.s0;
         lds_add(p, fA * (u * u * u) - Fprev);
-        k += 1.0;
+        k += R(1);
         ++p;
-        const double g = 3.0 * fA;
-        for (; k <= kLow; k += 1.0, ++p) {
+        const R g = R(3) * fA;
+        for (; k <= kLow; k += R(1), ++p) {
             u = k - Z.s0;
             lds_add(p, fma(u, fma(g, u, -g), fA));
         }
-        u = (k - 1.0) - Z.s0;
+        u = (k - R(1)) - Z.s0;
         Fprev = fA * (u * u * u);
     }
     // s1 < k < s2: F = c0 + c1 t + c2 t^2 + c3 t^3, t = k - s1;
     // step q0 + q1 t + q2 t^2
     if (k < Z.s2 && k <= kB) {
-        const double a = Z.s1 - Z.s0;
-        const double A = Z.r20 * Z.r30, B = Z.r20 * Z.r31;
-        const double c0 = frac * (A * a * a);
-        const double c1 = frac * (a * (A * (2.0 - Z.r31 * a) + B));
-        const double c2 = frac * (A * (1.0 - 2.0 * a * Z.r31) + B * (1.0 - a * Z.r21) + Z.r21 * Z.r31);
-        const double c3 = -frac * (A * Z.r31 + B * Z.r21);
-        double tt = k - Z.s1;
+        const R a = Z.s1 - Z.s0;
+        const R A = Z.r20 * Z.r30, B = Z.r20 * Z.r31;
+        const R c0 = frac * (A * a * a);
+        const R c1 = frac * (a * (A * (R(2) - Z.r31 * a) + B));
+        const R c2 = frac * (A * (R(1) - R(2) * a * Z.r31) + B * (R(1) - a * Z.r21) + Z.r21 * Z.r31);
+        const R c3 = -frac * (A * Z.r31 + B * Z.r21);
+        R tt = k - Z.s1;
         lds_add(p, fma(fma(fma(c3, tt, c2), tt, c1), tt, c0) - Fprev);
-        k += 1.0;
+        k += R(1);
         ++p;
-        const double q0 = c1 - c2 + c3, q1 = 2.0 * c2 - 3.0 * c3, q2 = 3.0 * c3;
-        for (; k < Z.s2 && k <= kB; k += 1.0, ++p) {
+        const R q0 = c1 - c2 + c3, q1 = R(2) * c2 - R(3) * c3, q2 = R(3) * c3;
+        for (; k < Z.s2 && k <= kB; k += R(1), ++p) {
             tt = k - Z.s1;
             lds_add(p, fma(fma(q2, tt, q1), tt, q0));
         }
-        tt = (k - 1.0) - Z.s1;
+        tt = (k - R(1)) - Z.s1;
         Fprev = fma(fma(fma(c3, tt, c2), tt, c1), tt, c0);
     }
     // s2 <= k: F = frac - fC w^3, w = s3 - k (frac once k >= s3);
     // step fC (3w^2 + 3w + 1) while k < s3
     if (k <= kB) {
-        const double fC = frac * Z.iC;
-        double w = Z.s3 - k;
-        lds_add(p, (w > 0.0 ? frac - fC * (w * w * w) : frac) - Fprev);
-        k += 1.0;
+        const R fC = frac * Z.iC;
+        R w = Z.s3 - k;
+        lds_add(p, (w > R(0) ? frac - fC * (w * w * w) : frac) - Fprev);
+        k += R(1);
         ++p;
-        const double g = 3.0 * fC;
-        for (; k < Z.s3 && k <= kB; k += 1.0, ++p) {
+        const R g = R(3) * fC;
+        for (; k < Z.s3 && k <= kB; k += R(1), ++p) {
             w = Z.s3 - k;
             lds_add(p, fma(w, fma(g, w, g), fC));
         }
         // the level whose upper plane passes s3
         if (k <= kB) {
-            w = Z.s3 - (k - 1.0);
+            w = Z.s3 - (k - R(1));
             lds_add(p, fC * (w * w * w));
         }
     }
@@ -366,7 +393,7 @@ __device__ __forceinline__ void column(const CTet& S, int a, int b, const Tile& 
         for (int k = 0; k < n2; ++k) {
             const double z[4] = {u0, k == 2 ? w0 : u1, k == 0 ? u2 : w1, w2};
             const double f2 = k == 0 ? s2.f0 : (k == 1 ? s2.f1 : s2.f2);
-            spread_z<WORK>(z, f1 * f2, t, Dcol, wc);
+            spread_z<WORK, double>(z, f1 * f2, t, Dcol, wc);
         }
     }
 }
@@ -379,18 +406,19 @@ __device__ __forceinline__ void column(const CTet& S, int a, int b, const Tile& 
 // wavefront produces the pieces of its own column, 0 to 9 of them; the z
 // walks then go over the lanes 64 pieces at a time, so a column cut into nine
 // pieces no longer holds the other 63 lanes back.
-template <int QCAP>
+template <int QCAP, typename R>
 struct PieceRing {
-    double z[4][QCAP];
-    double frac[QCAP];
+    R z[4][QCAP];
+    R frac[QCAP];
     int where[QCAP];  // D offset << 8 | tile
 };
 
 // The z walks of the next min(count, 64) queued pieces, one per lane.
 // Wave-uniform: every lane calls it with the same head and count.
-template <bool WORK, int QCAP>
-__device__ __forceinline__ void drain_round(PieceRing<QCAP>& Q, int& head, int& count,
-                                            const Tile* tiles, double* Dbuf, WorkCount& wc)
+template <bool WORK, int QCAP, typename R>
+__device__ __forceinline__ void drain_round(PieceRing<QCAP, R>& Q, int& head, int& count,
+                                            const Tile* tiles, R* Dbuf, WorkCount& wc,
+                                            bool local_z = false)
 {
     // the ring's records were written by other lanes of this wavefront: its
     // LDS accesses complete in issue order, so a wavefront fence (no wait on
@@ -402,10 +430,11 @@ __device__ __forceinline__ void drain_round(PieceRing<QCAP>& Q, int& head, int& 
     const int ntake = count < kWave ? count : kWave;
     if (lane < ntake) {
         const int q = (head + lane) & (QCAP - 1);
-        const double z[4] = {Q.z[0][q], Q.z[1][q], Q.z[2][q], Q.z[3][q]};
+        const R z[4] = {Q.z[0][q], Q.z[1][q], Q.z[2][q], Q.z[3][q]};
         const int w = Q.where[q];
-        const Tile& t = tiles[w & 0xFF];
-        spread_z<WORK>(z, Q.frac[q], t, Dbuf + (w >> 8), wc);
+        Tile t = tiles[w & 0xFF];
+        if (local_z) t.l0 = 0;  // heights relative to the tile's first level
+        spread_z<WORK, R>(z, Q.frac[q], t, Dbuf + (w >> 8), wc);
     }
     head = (head + ntake) & (QCAP - 1);
     count -= ntake;
@@ -419,7 +448,7 @@ __device__ __forceinline__ void drain_round(PieceRing<QCAP>& Q, int& head, int& 
 template <bool WORK, int QCAP>
 __device__ __forceinline__ void column_queue(bool valid, const CTet& S, int a, int b, const Tile& t,
                                              int tile_idx, int doff, double* Dbuf,
-                                             PieceRing<QCAP>& Q, int& head, int& count,
+                                             PieceRing<QCAP, double>& Q, int& head, int& count,
                                              const Tile* tiles, WorkCount& wc)
 {
     const int lane = threadIdx.x;
@@ -528,7 +557,250 @@ __device__ __forceinline__ void column_queue(bool valid, const CTet& S, int a, i
                 Q.where[q] = (doff << 8) | tile_idx;
             }
             count += __popcll(bal);
-            if (count >= kWave) drain_round<WORK, QCAP>(Q, head, count, tiles, Dbuf, wc);
+            if (count >= kWave) drain_round<WORK, QCAP, double>(Q, head, count, tiles, Dbuf, wc);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Slab form: the cells' volumes directly, each split computed once where
+// the pieces can be reused.  A tile row a (the slab a <= x < a+1 of the walk
+// frame) is cut from T once by x >= a and x <= a+1 (FP64 planes on the exact
+// bbox-local vertices); its <= 9 pieces are kept in LDS in FP32, relative to
+// the tile's first column and level.  Every column (a, b) of the row takes
+// them, splits each by y >= b and y <= b+1 in FP32 and sends the leaves to
+// the piece ring, whose z walks add each leaf's exact z distribution into the
+// column's cells: no cumulative values, so nothing cancels and FP32 keeps its
+// relative precision in every cell.
+// ---------------------------------------------------------------------------
+
+constexpr int kSlabPieces = 9;
+
+template <int ROWS>
+struct SlabCache {
+    float v[ROWS][kSlabPieces][4][2];  // (y - b0, z - l0) of the 4 vertices
+    float frac[ROWS][kSlabPieces];
+    int n[ROWS];
+};
+
+// Pieces of T cut by x >= a and x <= a+1 (walk frame, bbox-local vertices):
+// each inside part of the first cut is cut again.  The planes that do not
+// meet the bbox (a = 0, a + 1 = ext0) keep every vertex inside.
+template <int ROWS>
+__device__ __forceinline__ void slab_row(const CTet& S, int a, const Tile& t, int row,
+                                         SlabCache<ROWS>& C)
+{
+    const bool cut0 = a > 0, cut1 = a + 1 < S.ext[0];
+    double v[4][3];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[q][c] = S.vr[q][c];
+    double d0[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) d0[q] = cut0 ? v[q][0] - (double)a : 1.0;
+    Split<double> s0;
+    split_plane(d0, s0);
+    int n = 0;
+    if (s0.nin > 0) {
+        double U0[3], U1[3], U2[3], W0[3], W1[3], W2[3];
+        const bool a1 = s0.nin == 1, a2 = s0.nin == 2, a3 = s0.nin == 3, a4 = s0.nin == 4;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double va = sel4(v[0][c], v[1][c], v[2][c], v[3][c], s0.ia);
+            const double vb = sel4(v[0][c], v[1][c], v[2][c], v[3][c], s0.ib);
+            const double vc = sel4(v[0][c], v[1][c], v[2][c], v[3][c], s0.ic);
+            const double vd = sel4(v[0][c], v[1][c], v[2][c], v[3][c], s0.id);
+            const double in1 = a3 ? vb : va, in2 = a1 ? va : (a2 ? vb : vc);
+            const double out0 = a1 ? vb : (a2 ? vc : vd), out1 = a1 ? vc : vd, out2 = a2 ? vc : vd;
+            const double c0 = va + s0.t0 * (out0 - va);
+            const double c1 = in1 + s0.t1 * (out1 - in1);
+            const double c2 = in2 + s0.t2 * (out2 - in2);
+            const double c3 = vb + s0.t3 * (vd - vb);
+            U0[c] = va;
+            U1[c] = (a3 || a4) ? vb : c0;
+            U2[c] = (a3 || a4) ? vc : c1;
+            W0[c] = a2 ? vb : c0;
+            W1[c] = a2 ? c2 : c1;
+            W2[c] = a4 ? vd : (a2 ? c3 : c2);
+        }
+        const int n0 = (a2 || a3) ? 3 : 1;
+        for (int j = 0; j < n0; ++j) {
+            double cv[4][3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                cv[0][c] = U0[c];
+                cv[1][c] = j == 2 ? W0[c] : U1[c];
+                cv[2][c] = j == 0 ? U2[c] : W1[c];
+                cv[3][c] = W2[c];
+            }
+            const double f0 = j == 0 ? s0.f0 : (j == 1 ? s0.f1 : s0.f2);
+            double d1[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) d1[q] = cut1 ? (double)(a + 1) - cv[q][0] : 1.0;
+            Split<double> s1;
+            split_plane(d1, s1);
+            if (s1.nin == 0) continue;
+            const bool b1 = s1.nin == 1, b2 = s1.nin == 2, b3 = s1.nin == 3, b4 = s1.nin == 4;
+            float u0[2], u1[2], u2[2], w0[2], w1[2], w2[2];
+            const double org[2] = {(double)t.b0, (double)t.l0};
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const double va = sel4(cv[0][c + 1], cv[1][c + 1], cv[2][c + 1], cv[3][c + 1], s1.ia);
+                const double vb = sel4(cv[0][c + 1], cv[1][c + 1], cv[2][c + 1], cv[3][c + 1], s1.ib);
+                const double vc = sel4(cv[0][c + 1], cv[1][c + 1], cv[2][c + 1], cv[3][c + 1], s1.ic);
+                const double vd = sel4(cv[0][c + 1], cv[1][c + 1], cv[2][c + 1], cv[3][c + 1], s1.id);
+                const double in1 = b3 ? vb : va, in2 = b1 ? va : (b2 ? vb : vc);
+                const double out0 = b1 ? vb : (b2 ? vc : vd), out1 = b1 ? vc : vd, out2 = b2 ? vc : vd;
+                const double c0 = va + s1.t0 * (out0 - va);
+                const double c1 = in1 + s1.t1 * (out1 - in1);
+                const double c2 = in2 + s1.t2 * (out2 - in2);
+                const double c3 = vb + s1.t3 * (vd - vb);
+                u0[c] = (float)(va - org[c]);
+                u1[c] = (float)(((b3 || b4) ? vb : c0) - org[c]);
+                u2[c] = (float)(((b3 || b4) ? vc : c1) - org[c]);
+                w0[c] = (float)((b2 ? vb : c0) - org[c]);
+                w1[c] = (float)((b2 ? c2 : c1) - org[c]);
+                w2[c] = (float)((b4 ? vd : (b2 ? c3 : c2)) - org[c]);
+            }
+            const int n1 = (b2 || b3) ? 3 : 1;
+            for (int k = 0; k < n1; ++k, ++n) {
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    C.v[row][n][0][c] = u0[c];
+                    C.v[row][n][1][c] = k == 2 ? w0[c] : u1[c];
+                    C.v[row][n][2][c] = k == 0 ? u2[c] : w1[c];
+                    C.v[row][n][3][c] = w2[c];
+                }
+                C.frac[row][n] = (float)(f0 * (k == 0 ? s1.f0 : (k == 1 ? s1.f1 : s1.f2)));
+            }
+        }
+    }
+    C.n[row] = n;
+}
+
+// Column (a, b) of the slab form (valid lanes only; every lane calls it):
+// zeroes the column's cells, splits the row's slab pieces by y >= b and
+// y <= b+1 and queues the leaves; full rounds of 64 are walked as they fill.
+template <bool WORK, int QCAP, int ROWS>
+__device__ __forceinline__ void column_slab(bool valid, const CTet& S, int b, const Tile& t,
+                                            int tile_idx, int row, int doff, float* Dbuf,
+                                            const SlabCache<ROWS>& C, PieceRing<QCAP, float>& Q,
+                                            int& head, int& count, const Tile* tiles, WorkCount& wc)
+{
+    const int lane = threadIdx.x;
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+    int ns = 0;
+    if (valid) {
+        float* Dcol = Dbuf + doff;
+        for (int l = 0; l < t.tl; ++l) Dcol[l] = 0.0f;
+        ns = C.n[row];
+    }
+    // the wavefront's largest slab piece count (at most 9)
+    int nsmax = ns;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) nsmax = max(nsmax, __shfl_xor(nsmax, off, kWave));
+    const bool cut0 = b > 0, cut1 = b + 1 < S.ext[1];
+    const float yb = (float)(b - t.b0);  // the column's lower y plane, tile-relative
+    for (int p = 0; p < nsmax; ++p) {
+        int n1 = 0;
+        Split<float> s1;
+        float U0[2], U1[2], U2[2], W0[2], W1[2], W2[2];
+        float fp = 0.0f;
+        if (p < ns) {
+            float v[4][2];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                v[q][0] = C.v[row][p][q][0] - yb;  // column-local y
+                v[q][1] = C.v[row][p][q][1];
+            }
+            fp = C.frac[row][p];
+            float d[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) d[q] = cut0 ? v[q][0] : 1.0f;
+            split_plane(d, s1);
+            if (s1.nin > 0) {
+                const bool a1 = s1.nin == 1, a2 = s1.nin == 2, a3 = s1.nin == 3, a4 = s1.nin == 4;
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const float va = sel4(v[0][c], v[1][c], v[2][c], v[3][c], s1.ia);
+                    const float vb = sel4(v[0][c], v[1][c], v[2][c], v[3][c], s1.ib);
+                    const float vc = sel4(v[0][c], v[1][c], v[2][c], v[3][c], s1.ic);
+                    const float vd = sel4(v[0][c], v[1][c], v[2][c], v[3][c], s1.id);
+                    const float in1 = a3 ? vb : va, in2 = a1 ? va : (a2 ? vb : vc);
+                    const float out0 = a1 ? vb : (a2 ? vc : vd), out1 = a1 ? vc : vd, out2 = a2 ? vc : vd;
+                    const float c0 = va + s1.t0 * (out0 - va);
+                    const float c1 = in1 + s1.t1 * (out1 - in1);
+                    const float c2 = in2 + s1.t2 * (out2 - in2);
+                    const float c3 = vb + s1.t3 * (vd - vb);
+                    U0[c] = va;
+                    U1[c] = (a3 || a4) ? vb : c0;
+                    U2[c] = (a3 || a4) ? vc : c1;
+                    W0[c] = a2 ? vb : c0;
+                    W1[c] = a2 ? c2 : c1;
+                    W2[c] = a4 ? vd : (a2 ? c3 : c2);
+                }
+                n1 = (a2 || a3) ? 3 : 1;
+                if constexpr (WORK) wc.xpiece += (unsigned long long)n1;
+            }
+        }
+        const int nj = __ballot(n1 == 3) ? 3 : (__ballot(n1 == 1) ? 1 : 0);
+        for (int j = 0; j < nj; ++j) {
+            int n2 = 0;
+            Split<float> s2;
+            float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f, w0 = 0.0f, w1 = 0.0f, w2 = 0.0f, f1 = 0.0f;
+            if (j < n1) {
+                float cv[4][2];
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    cv[0][c] = U0[c];
+                    cv[1][c] = j == 2 ? W0[c] : U1[c];
+                    cv[2][c] = j == 0 ? U2[c] : W1[c];
+                    cv[3][c] = W2[c];
+                }
+                f1 = fp * (j == 0 ? s1.f0 : (j == 1 ? s1.f1 : s1.f2));
+                float d[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) d[q] = cut1 ? 1.0f - cv[q][0] : 1.0f;
+                split_plane(d, s2);
+                if (s2.nin > 0) {
+                    const float za = sel4(cv[0][1], cv[1][1], cv[2][1], cv[3][1], s2.ia);
+                    const float zb = sel4(cv[0][1], cv[1][1], cv[2][1], cv[3][1], s2.ib);
+                    const float zc = sel4(cv[0][1], cv[1][1], cv[2][1], cv[3][1], s2.ic);
+                    const float zd = sel4(cv[0][1], cv[1][1], cv[2][1], cv[3][1], s2.id);
+                    const bool b1 = s2.nin == 1, b2 = s2.nin == 2, b3 = s2.nin == 3, b4 = s2.nin == 4;
+                    const float in1 = b3 ? zb : za, in2 = b1 ? za : (b2 ? zb : zc);
+                    const float out0 = b1 ? zb : (b2 ? zc : zd), out1 = b1 ? zc : zd, out2 = b2 ? zc : zd;
+                    const float c0 = za + s2.t0 * (out0 - za);
+                    const float c1 = in1 + s2.t1 * (out1 - in1);
+                    const float c2 = in2 + s2.t2 * (out2 - in2);
+                    const float c3 = zb + s2.t3 * (zd - zb);
+                    u0 = za;
+                    u1 = (b3 || b4) ? zb : c0;
+                    u2 = (b3 || b4) ? zc : c1;
+                    w0 = b2 ? zb : c0;
+                    w1 = b2 ? c2 : c1;
+                    w2 = b4 ? zd : (b2 ? c3 : c2);
+                    n2 = (b2 || b3) ? 3 : 1;
+                    if constexpr (WORK) wc.piece += (unsigned long long)n2;
+                }
+            }
+            const int nk = __ballot(n2 == 3) ? 3 : (__ballot(n2 == 1) ? 1 : 0);
+            for (int k = 0; k < nk; ++k) {
+                const bool has = k < n2;
+                const uint64_t bal = __ballot(has);
+                if (has) {
+                    const int q = (head + count + __popcll(bal & below)) & (QCAP - 1);
+                    Q.z[0][q] = u0;
+                    Q.z[1][q] = k == 2 ? w0 : u1;
+                    Q.z[2][q] = k == 0 ? u2 : w1;
+                    Q.z[3][q] = w2;
+                    Q.frac[q] = f1 * (k == 0 ? s2.f0 : (k == 1 ? s2.f1 : s2.f2));
+                    Q.where[q] = (doff << 8) | tile_idx;
+                }
+                count += __popcll(bal);
+                if (count >= kWave) drain_round<WORK, QCAP, float>(Q, head, count, tiles, Dbuf, wc, true);
+            }
         }
     }
 }
@@ -672,19 +944,26 @@ __device__ __forceinline__ void flush_mass(const BoxDesc& P, double& macc)
 // 1 to 9 pieces walking up to tens of levels each; 8 tets with 1408 entries
 // and no ring is the same walk with each column's pieces on its own lane.
 // The 2048-entry instance runs at two per SIMD.
-template <typename OutT, int CAP, int GROUP, int TILES, bool WORK, int QCAP>
-__global__ __launch_bounds__(kWave, (CAP <= 1408 ? 3 : 2)) void queue_kernel(QueueArgs Q)
+// SLAB selects the slab form (FP32 cell volumes, CAP FP32 entries, at most
+// SLAB_ROWS tile rows a batch); otherwise the cumulative walk in FP64.
+template <typename OutT, int CAP, int GROUP, int TILES, bool WORK, int QCAP, bool SLAB = false>
+__global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) void queue_kernel(QueueArgs Q)
 {
     static_assert(kWave % GROUP == 0 && GROUP <= kWave && TILES <= GROUP, "chunk of whole groups");
     static_assert(QCAP == 0 || (QCAP >= 2 * kWave && (QCAP & (QCAP - 1)) == 0 && TILES <= 256 &&
                                 CAP < (1 << 23)), "piece ring: a power of two of at least 128");
+    static_assert(!SLAB || (QCAP > 0 && GROUP < 16), "the slab form queues its leaves");
+    using DT = typename std::conditional<SLAB, float, double>::type;
+    constexpr int SLAB_ROWS = SLAB ? 16 : 1;
     __shared__ CTet slots[GROUP];
-    __shared__ double Dbuf[CAP];
+    __shared__ DT Dbuf[CAP];
     __shared__ Tile tiles[TILES];
     __shared__ int t_slot[TILES];
     __shared__ int64_t s_incl[TILES];
     __shared__ int64_t s_item;
-    __shared__ PieceRing<(QCAP > 0 ? QCAP : 1)> ring;
+    __shared__ PieceRing<(QCAP > 0 ? QCAP : 1), DT> ring;
+    __shared__ SlabCache<SLAB_ROWS> slab;
+    __shared__ int s_row0[SLAB ? TILES : 1];
 
     const int lane = threadIdx.x;
     double macc = 0.0;
@@ -747,7 +1026,7 @@ __global__ __launch_bounds__(kWave, (CAP <= 1408 ? 3 : 2)) void queue_kernel(Que
             // With 16-tet groups (small tets, many per batch) runs of
             // untiled tetrahedra are laid out by all lanes at once: one slot
             // per lane and a scan of their D sizes.
-            int nt = 0, used = 0;
+            int nt = 0, used = 0, rows = 0;
             while (cur < GROUP && nt < TILES) {
                 if constexpr (GROUP >= 16) {
                     if (cur_tile == 0 && slots[cur].ncell <= CAP) {
@@ -797,22 +1076,30 @@ __global__ __launch_bounds__(kWave, (CAP <= 1408 ? 3 : 2)) void queue_kernel(Que
                 }
                 Tile t;
                 int ntiles = 1;
-                if (S.ncell <= CAP) {
+                if (S.ncell <= CAP && (!SLAB || S.ext[0] <= SLAB_ROWS)) {
                     t.a0 = 0; t.ta = S.ext[0]; t.b0 = 0; t.tb = S.ext[1];
                     t.l0 = 0; t.tl = S.ext[2]; t.ha = 0; t.hb = 0;
                 } else {
                     int ta, tb, tl;
-                    tile_shape<CAP>(S, ta, tb, tl, ntiles);
+                    if constexpr (SLAB) tile_shape_slab<CAP>(S, SLAB_ROWS, ta, tb, tl, ntiles);
+                    else tile_shape<CAP>(S, ta, tb, tl, ntiles);
                     const int nx = (S.ext[0] + ta - 1) / ta, ny = (S.ext[1] + tb - 1) / tb;
                     const int ix = cur_tile % nx, iy = (cur_tile / nx) % ny, iz = cur_tile / (nx * ny);
                     t.a0 = ix * ta; t.ta = min(ta, S.ext[0] - t.a0);
                     t.b0 = iy * tb; t.tb = min(tb, S.ext[1] - t.b0);
                     t.l0 = iz * tl; t.tl = min(tl, S.ext[2] - t.l0);
-                    t.ha = t.a0 > 0 ? 1 : 0;
-                    t.hb = t.b0 > 0 ? 1 : 0;
+                    // the cumulative walk differences against the neighbour
+                    // column below; the slab form needs none
+                    t.ha = (!SLAB && t.a0 > 0) ? 1 : 0;
+                    t.hb = (!SLAB && t.b0 > 0) ? 1 : 0;
                 }
                 const int ds = tile_dsize(t);
                 if (used + ds > CAP) break;  // buffer full: run this batch first
+                if (SLAB && rows + t.ta > SLAB_ROWS) break;  // row cache full
+                if constexpr (SLAB) {
+                    if (lane == 0) s_row0[nt] = rows;
+                    rows += t.ta;
+                }
                 t.doff = used;
                 t.inv_wb = 1.0f / (float)(t.tb + t.hb);
                 t.inv_tb = 1.0f / (float)t.tb;
@@ -858,6 +1145,19 @@ __global__ __launch_bounds__(kWave, (CAP <= 1408 ? 3 : 2)) void queue_kernel(Que
                     }
                     r = (int)(idx - (s_incl[lo] - tile_cols(tiles[lo])));
                 };
+                if constexpr (SLAB) {
+                    // The slab pieces of every tile row of the batch, one row
+                    // per lane (rows <= SLAB_ROWS <= 64).
+                    int nrows = 0;
+                    for (int k = 0; k < nt; ++k) nrows += tiles[k].ta;
+                    if (lane < nrows) {
+                        int k = 0;
+                        while (k + 1 < nt && s_row0[k + 1] <= lane) ++k;
+                        const Tile t = tiles[k];
+                        slab_row<SLAB_ROWS>(slots[t_slot[k]], t.a0 + (lane - s_row0[k]), t, lane, slab);
+                    }
+                    __syncthreads();
+                }
                 if constexpr (QCAP > 0) {
                     // Phase 1 for every window of the batch, the pieces of all
                     // columns walked 64 at a time; phase 2 follows once the
@@ -874,14 +1174,20 @@ __global__ __launch_bounds__(kWave, (CAP <= 1408 ? 3 : 2)) void queue_kernel(Que
                         const int qa = fdivi(r, t.inv_wb);
                         const int a = t.a0 - t.ha + qa;
                         const int b = t.b0 - t.hb + (r - qa * wb);
-                        column_queue<WORK, QCAP>(valid, S, a, b, t, lo, t.doff + r * t.tl, Dbuf,
-                                                 ring, head, count, tiles, wc);
+                        if constexpr (SLAB)
+                            column_slab<WORK, QCAP, SLAB_ROWS>(valid, S, b, t, lo, s_row0[lo] + qa,
+                                                               t.doff + r * t.tl, Dbuf, slab, ring,
+                                                               head, count, tiles, wc);
+                        else
+                            column_queue<WORK, QCAP>(valid, S, a, b, t, lo, t.doff + r * t.tl, Dbuf,
+                                                     ring, head, count, tiles, wc);
                         if (valid) {
                             ++n_col;
                             if constexpr (WORK) n_colcell += (unsigned long long)t.tl;
                         }
                     }
-                    while (count > 0) drain_round<WORK, QCAP>(ring, head, count, tiles, Dbuf, wc);
+                    while (count > 0)
+                        drain_round<WORK, QCAP, DT>(ring, head, count, tiles, Dbuf, wc, SLAB);
                     __syncthreads();
                 }
                 for (int64_t base = 0; base < total; base += kWave) {
@@ -896,7 +1202,7 @@ __global__ __launch_bounds__(kWave, (CAP <= 1408 ? 3 : 2)) void queue_kernel(Que
                             const int qa = fdivi(r, t.inv_wb);
                             const int a = t.a0 - t.ha + qa;
                             const int b = t.b0 - t.hb + (r - qa * wb);
-                            column<WORK>(S, a, b, t, Dbuf + t.doff + r * t.tl, wc);
+                            if constexpr (!SLAB) column<WORK>(S, a, b, t, Dbuf + t.doff + r * t.tl, wc);
                             ++n_col;
                             if constexpr (WORK) n_colcell += (unsigned long long)t.tl;
                         }
@@ -911,11 +1217,12 @@ __global__ __launch_bounds__(kWave, (CAP <= 1408 ? 3 : 2)) void queue_kernel(Que
                         const int ca = fdivi(r, t.inv_wb), cb = r - ca * wb;
                         const int i = ca - t.ha, j = cb - t.hb;
                         if (i >= 0 && j >= 0) {
-                            const bool has_a = (t.a0 + i) > 0, has_b = (t.b0 + j) > 0;
-                            const double* D11 = Dbuf + t.doff + r * t.tl;
-                            const double* D01 = D11 - wb * t.tl;
-                            const double* D10 = D11 - t.tl;
-                            const double* D00 = D01 - t.tl;
+                            // the slab form holds the cells' own volumes: no differences
+                            const bool has_a = !SLAB && (t.a0 + i) > 0, has_b = !SLAB && (t.b0 + j) > 0;
+                            const DT* D11 = Dbuf + t.doff + r * t.tl;
+                            const DT* D01 = D11 - wb * t.tl;
+                            const DT* D10 = D11 - t.tl;
+                            const DT* D00 = D01 - t.tl;
                             // grid cell of level 0, and the grid axis the levels walk
                             const int o0 = t.a0 + i, o1 = t.b0 + j, o2 = t.l0;
                             const int k0 = walk_axis(S, 0), k1 = walk_axis(S, 1), k2 = walk_axis(S, 2);
@@ -1168,11 +1475,16 @@ const void* queue_kernel_for(int cap)
     return reinterpret_cast<const void*>(&queue_kernel<OutT, 2048, 32, 32, WORK, 0>);
 }
 
+// The slab form (PSD_METHOD_SLAB): 2048 FP32 entries, 16 tile rows a batch,
+// 8-tet groups, 128-leaf ring; FP32 grids only, no work counters.
+const void* slab_kernel() { return reinterpret_cast<const void*>(&queue_kernel<float, 2048, 8, 8, false, 128, true>); }
+
 template <typename OutT, bool WORK>
-hipError_t launch_queue_kernel(const QueueArgs& Q, int cap, int grid, hipStream_t stream)
+hipError_t launch_queue_kernel(const QueueArgs& Q, int cap, bool slab, int grid, hipStream_t stream)
 {
-    hipLaunchKernelGGL(reinterpret_cast<void (*)(QueueArgs)>(const_cast<void*>(queue_kernel_for<OutT, WORK>(cap))),
-                       dim3(grid), dim3(kWave), 0, stream, Q);
+    const void* k = slab ? slab_kernel() : queue_kernel_for<OutT, WORK>(cap);
+    hipLaunchKernelGGL(reinterpret_cast<void (*)(QueueArgs)>(const_cast<void*>(k)), dim3(grid), dim3(kWave),
+                       0, stream, Q);
     return hipGetLastError();
 }
 
@@ -1185,6 +1497,7 @@ Tuning default_tuning()
     t.waves_per_cu = 0;  // as many as fit a compute unit
     t.ordered = 0;
     t.work_counters = 0;
+    t.slab = 0;
     return t;
 }
 
@@ -1202,8 +1515,20 @@ int auto_cap(const BoxDesc* boxes, int n_boxes)
     return ratio >= 1.5 ? 1024 : 960;
 }
 
-hipError_t queue_resident_waves(int cap, bool out_fp64, int& waves, bool work)
+hipError_t queue_resident_waves(int cap, bool out_fp64, int& waves, bool work, bool slab)
 {
+    if (slab) {
+        static std::atomic<int> known_slab{0};
+        int n = known_slab.load(std::memory_order_relaxed);
+        if (n == 0) {
+            const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, slab_kernel(), kWave, 0);
+            if (e != hipSuccess) return e;
+            if (n < 1) n = 1;
+            known_slab.store(n, std::memory_order_relaxed);
+        }
+        waves = n;
+        return hipSuccess;
+    }
     // one kernel instance per (buffer size, output type, counters); the
     // answer only depends on the instance, so it is asked once
     static std::atomic<int> known[5][2][2];
@@ -1298,20 +1623,22 @@ hipError_t launch_queue(const BoxDesc* boxes_in, int n_boxes, bool out_fp64, con
         cus < 1)
         cus = 256;
     const int cap = tune.cap > 0 ? tune.cap : auto_cap(boxes, n_boxes);
-    const bool work = tune.work_counters != 0 && stats != nullptr;
+    const bool slab = tune.slab != 0;
+    if (slab && out_fp64) return hipErrorInvalidValue;  // the slab form writes FP32 grids
+    const bool work = tune.work_counters != 0 && stats != nullptr && !slab;
     int waves = tune.waves_per_cu;
     if (waves <= 0) {
-        const hipError_t e = queue_resident_waves(cap, out_fp64, waves, work);
+        const hipError_t e = queue_resident_waves(cap, out_fp64, waves, work, slab);
         if (e != hipSuccess) return e;
     }
     int64_t grid = (int64_t)cus * waves;
     if (grid > n_chunks) grid = n_chunks;
     if (grid < 1) grid = 1;
     if (work)
-        return out_fp64 ? launch_queue_kernel<double, true>(Q, cap, (int)grid, stream)
-                        : launch_queue_kernel<float, true>(Q, cap, (int)grid, stream);
-    return out_fp64 ? launch_queue_kernel<double, false>(Q, cap, (int)grid, stream)
-                    : launch_queue_kernel<float, false>(Q, cap, (int)grid, stream);
+        return out_fp64 ? launch_queue_kernel<double, true>(Q, cap, slab, (int)grid, stream)
+                        : launch_queue_kernel<float, true>(Q, cap, slab, (int)grid, stream);
+    return out_fp64 ? launch_queue_kernel<double, false>(Q, cap, slab, (int)grid, stream)
+                    : launch_queue_kernel<float, false>(Q, cap, slab, (int)grid, stream);
 }
 
 }  // namespace psd

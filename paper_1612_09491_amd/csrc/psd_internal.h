@@ -71,6 +71,7 @@ struct Tuning {
     int waves_per_cu;   // persistent workgroups per compute unit (0: as many as fit)
     int ordered;        // 1: chunks in decreasing estimated cost
     int work_counters;  // 1: the instrumented kernel, adding work events into stats[8..11]
+    int slab;           // 1: the slab form (FP32 cell volumes from cached slab pieces)
 };
 
 struct QueueArgs {
@@ -94,7 +95,8 @@ hipError_t launch_queue(const BoxDesc* boxes, int n_boxes, bool out_fp64, const 
                         void* ws, size_t ws_bytes, unsigned long long* stats, hipStream_t stream);
 Tuning default_tuning();
 // Wavefronts of the deposit kernel with this buffer that fit one compute unit.
-hipError_t queue_resident_waves(int cap, bool out_fp64, int& waves, bool work = false);
+hipError_t queue_resident_waves(int cap, bool out_fp64, int& waves, bool work = false,
+                                bool slab = false);
 
 // Number of NaN or infinite values among p[0..n) (a device array), counted
 // on `stream` into the device word dcount and returned in host_count;

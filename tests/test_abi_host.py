@@ -160,3 +160,16 @@ def test_check_finite_flag_is_accepted(psd):
     assert psd.PSD_CHECK_FINITE == 1 << 5
     assert psd.uniform_workspace_size((8, 8, 8), 16, flags=psd.PSD_CHECK_FINITE) > 0
     assert psd.STAT_NAMES[7] == "dropped_nonfinite"
+
+
+def test_slab_flag_combinations(psd):
+    """PSD_METHOD_SLAB (FP32 cell volumes) is accepted alone and with the output flags, and
+    refused with an FP64 grid, the per-cell method, the surrogate or the work counters."""
+    assert psd.PSD_METHOD_SLAB == 1 << 7
+    ok = (0, psd.PSD_OUT_DENSITY, psd.PSD_ACCUMULATE, psd.PSD_CHECK_FINITE)
+    for extra in ok:
+        assert psd.uniform_workspace_size((8, 8, 8), 16, flags=psd.PSD_METHOD_SLAB | extra) > 0
+    for bad in (psd.PSD_PREC_FP64, psd.PSD_METHOD_CELL, psd.PSD_SURROGATE, psd.PSD_WORK_COUNTERS):
+        with pytest.raises(psd.PsdError) as e:
+            psd.uniform_workspace_size((8, 8, 8), 16, flags=psd.PSD_METHOD_SLAB | bad)
+        assert e.value.code == psd.PSD_ERR_UNSUPPORTED

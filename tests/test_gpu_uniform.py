@@ -1,10 +1,11 @@
 """GPU parity of psd_deposit_uniform against the FP64 oracle.
 
-Both methods are checked: the default cumulative method (FP64 arithmetic) and
-the per-cell cell-local FP32 clip (PSD_METHOD_CELL).  Tolerances: an FP32
-output grid or FP32 clipping within 1e-5 relative L1 and Linf of the
-oracle's densities; FP64 arithmetic into an FP64 grid within 1e-12.  Integer
-counters (tets, bbox pairs, inverted, zero-volume) must match exactly.
+Three methods are checked: the default cumulative method (FP64 arithmetic),
+the per-cell cell-local FP32 clip (PSD_METHOD_CELL) and the cached slab clip in
+FP32 (PSD_METHOD_SLAB).  Tolerances: an FP32 output grid or FP32 clipping
+within 1e-5 relative L1 and Linf of the oracle's densities; FP64 arithmetic
+into an FP64 grid within 1e-12.  Integer counters (tets, bbox pairs, inverted,
+zero-volume) must match exactly.
 """
 
 import functools
@@ -58,7 +59,8 @@ def _check_stats(st, cnt):
     assert st[5] == cnt["n_degenerate"]
 
 
-METHODS = {"cumulative": 0, "cell": 8}  # 8 = PSD_METHOD_CELL
+METHODS = {"cumulative": 0, "cell": 8, "slab": 128}  # PSD_METHOD_CELL, PSD_METHOD_SLAB
+FP64_METHODS = {"cumulative": 0, "cell": 8}  # the methods with FP64 arithmetic into FP64 grids
 
 
 @pytest.mark.parametrize("method", list(METHODS))
@@ -74,12 +76,12 @@ def test_zel32_g64_fp32(psd, orc, seed, method):
     _check_stats(st, cnt)
 
 
-@pytest.mark.parametrize("method", list(METHODS))
+@pytest.mark.parametrize("method", list(FP64_METHODS))
 @pytest.mark.parametrize("seed", [1, 2])
 def test_zel32_g64_fp64(psd, orc, seed, method):
     pos, p = workload("zel32_g64", seed=seed)
     ref, cnt = orc.deposit_uniform(pos, p["nc"])
-    got, msum, st = _run(psd, pos, p["nc"], flags=psd.PSD_PREC_FP64 | METHODS[method])
+    got, msum, st = _run(psd, pos, p["nc"], flags=psd.PSD_PREC_FP64 | FP64_METHODS[method])
     assert _rel_l1(got, ref) <= FP64_L1 and _rel_linf(got, ref) <= FP64_LINF
     assert abs(msum - 1.0) <= 1e-12
     _check_stats(st, cnt)
@@ -91,8 +93,9 @@ def test_undisplaced_lattice_is_uniform(psd, nc, method):
     pos = lattice_positions(32)
     got, _, st = _run(psd, pos, nc, flags=METHODS[method])
     assert np.max(np.abs(got * nc ** 3 - 1.0)) <= 1e-5
-    got64, _, _ = _run(psd, pos, nc, flags=psd.PSD_PREC_FP64 | METHODS[method])
-    assert np.max(np.abs(got64 * nc ** 3 - 1.0)) <= 1e-12
+    if method in FP64_METHODS:
+        got64, _, _ = _run(psd, pos, nc, flags=psd.PSD_PREC_FP64 | METHODS[method])
+        assert np.max(np.abs(got64 * nc ** 3 - 1.0)) <= 1e-12
 
 
 def _compare(psd, orc, pos, nc, box=1.0, mass=1.0, l1=FP32_L1):
@@ -100,10 +103,12 @@ def _compare(psd, orc, pos, nc, box=1.0, mass=1.0, l1=FP32_L1):
     for m in METHODS.values():
         got, msum, st = _run(psd, pos, nc, box=box, mass=mass, flags=m)
         assert _rel_l1(got, ref) <= l1, (m, _rel_l1(got, ref))
+        _check_stats(st, cnt)
+        if m not in FP64_METHODS.values():
+            continue
         got64, msum64, _ = _run(psd, pos, nc, flags=psd.PSD_PREC_FP64 | m, box=box, mass=mass)
         assert _rel_l1(got64, ref) <= FP64_L1, (m, _rel_l1(got64, ref))
         assert abs(msum64 - mass) <= 1e-12 * abs(mass)
-        _check_stats(st, cnt)
     return got, ref
 
 
@@ -165,6 +170,21 @@ def test_huge_tets_tiled_in_every_instance(psd, orc, tuning):
     out = psd.deposit_uniform(pt, 48, flags=psd.PSD_PREC_FP64, stats=st, tuning=tuning)
     assert _rel_l1(out.cpu().numpy(), ref) <= FP64_L1
     assert int(st[0].item()) == 6 * 4 ** 3
+
+
+def test_huge_tets_tiled_in_the_slab_form(psd, orc):
+    """The slab form tiles tetrahedra whose bbox exceeds its 2048-entry buffer or its 16
+    cached rows: the FP32 cell volumes still meet the FP32 bar, whose error does not grow
+    with the tetrahedron's size (no differences of cumulative values)."""
+    pos = zeldovich_positions(4, 1.4, seed=44)
+    biggest = _max_bbox_cells(orc, pos, 48)
+    assert biggest > 2048, biggest
+    ref, _ = orc.deposit_uniform(pos, 48)
+    got, msum, st = _run(psd, pos, 48, flags=psd.PSD_METHOD_SLAB)
+    l1, linf = _rel_l1(got, ref), _rel_linf(got, ref)
+    print(f"slab, tets up to {biggest} bbox cells: L1 {l1:.3e} Linf {linf:.3e} mass {msum - 1:.3e}")
+    assert l1 <= FP32_L1 and linf <= FP32_LINF
+    assert abs(msum - 1.0) <= 1e-6
 
 
 def test_zel64_g16_full_grid(psd, orc):
