@@ -837,10 +837,14 @@ __device__ __forceinline__ int nth_bit(uint64_t m, int k)
 // Builds tetrahedron `tid` of box P into slot S; returns its bbox cell count
 // (0 when nothing is left to do) and deposits the cases that need no walk.
 template <typename OutT>
+// With `pend` (the group-tile instances), a tetrahedron whose whole mass goes
+// to one cell (inside one cell, or zero volume) is not added here: its cell
+// (wrapped grid coordinates) is returned in pend[0..2] and pend[3] = 1, and
+// the caller adds it to the group's tile.
 __device__ __forceinline__ int setup_tet(const BoxDesc& P, int64_t tid, CTet& S, double& macc,
                                          unsigned long long& n_pair, unsigned long long& n_nz,
                                          unsigned long long& n_inv, unsigned long long& n_deg,
-                                         unsigned long long* stats)
+                                         unsigned long long* stats, int* pend = nullptr)
 {
     const int64_t cube = tid / 6;
     const int p = (int)(tid - cube * 6);
@@ -871,7 +875,14 @@ __device__ __forceinline__ int setup_tet(const BoxDesc& P, int64_t tid, CTet& S,
         const int64_t idx = out_index(P, g[0], g[1], g[2]);
         if (idx >= 0) {
             ++n_nz;
-            atomicAdd(out + idx, (OutT)(P.m * P.out_scale));
+            if (pend) {
+                pend[0] = g[0];
+                pend[1] = g[1];
+                pend[2] = g[2];
+                pend[3] = 1;
+            } else {
+                atomicAdd(out + idx, (OutT)(P.m * P.out_scale));
+            }
             macc += P.m;
         }
         return 0;
@@ -917,7 +928,14 @@ __device__ __forceinline__ int setup_tet(const BoxDesc& P, int64_t tid, CTet& S,
         const int64_t idx = out_index(P, S.lo[0], S.lo[1], S.lo[2]);
         if (idx >= 0) {
             ++n_nz;
-            atomicAdd(out + idx, (OutT)(P.m * P.out_scale));
+            if (pend) {
+                pend[0] = S.lo[0];
+                pend[1] = S.lo[1];
+                pend[2] = S.lo[2];
+                pend[3] = 1;
+            } else {
+                atomicAdd(out + idx, (OutT)(P.m * P.out_scale));
+            }
             macc += P.m;
         }
         ncell = 0;
@@ -964,6 +982,14 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
     __shared__ PieceRing<(QCAP > 0 ? QCAP : 1), DT> ring;
     __shared__ SlabCache<SLAB_ROWS> slab;
     __shared__ int s_row0[SLAB ? TILES : 1];
+    // Small tetrahedra (the <= 960-entry instances): a group's tets come from
+    // neighbouring Lagrangian cubes and share most of their cells, so their
+    // masses are summed in an LDS tile over the group's union bbox and each
+    // non-zero cell is flushed with one global atomic (a group whose union is
+    // larger than the tile adds straight to the grid).
+    constexpr bool AGG = CAP <= 960 && QCAP == 0 && !SLAB;
+    constexpr int ACC = AGG ? 192 : 1;
+    __shared__ OutT acc[ACC];
 
     const int lane = threadIdx.x;
     double macc = 0.0;
@@ -1010,13 +1036,85 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
         for (int grp = 0; grp * GROUP < ntodo; ++grp) {
         const int k = grp * GROUP + lane;  // rank among the chunk's tets to do
         int ncell = 0;
+        int pend[4] = {0, 0, 0, 0};
         if (lane < GROUP && k < ntodo) {
             const int64_t tid = first + (P.exact_mask ? nth_bit(todo, k) : k);
             ncell = setup_tet<OutT>(P, tid, slots[lane], macc, n_pair, n_nz, n_inv, n_deg,
-                                    Q.stats);
+                                    Q.stats, AGG ? pend : nullptr);
         }
         if (lane < GROUP) slots[lane].ncell = ncell;
         __syncthreads();
+        // The group tile: origin gref (wrapped grid cell of the first tet with
+        // anything to add), box [gmn, gmn + gE) relative to it (minimum image).
+        int gref[3] = {0, 0, 0}, gmn[3] = {0, 0, 0}, gE[3] = {1, 1, 1};
+        bool tiled = false;
+        if constexpr (AGG) {
+            int lo_l[3] = {0, 0, 0}, hi_l[3] = {0, 0, 0};
+            bool has = false;
+            if (lane < GROUP && ncell > 0) {
+                const CTet& S = slots[lane];
+                has = true;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    const int c = walk_axis(S, q);
+                    lo_l[c] = S.lo[c];
+                    hi_l[c] = S.ext[q] - 1;
+                }
+            } else if (pend[3]) {
+                has = true;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) lo_l[c] = pend[c];
+            }
+            const uint64_t hb = __ballot(has);
+            if (hb) {
+                const int src = __ffsll((long long)hb) - 1;
+                int mn[3], mx[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    gref[c] = __shfl(lo_l[c], src, kWave);
+                    const int nca = P.nc[c];
+                    int d = lo_l[c] - gref[c];
+                    if (2 * d > nca) d -= nca;
+                    else if (2 * d < -nca) d += nca;
+                    mn[c] = has ? d : 0x3FFFFFFF;
+                    mx[c] = has ? d + hi_l[c] : -0x3FFFFFFF;
+                }
+#pragma unroll
+                for (int off = kWave / 2; off > 0; off >>= 1)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        mn[c] = min(mn[c], __shfl_xor(mn[c], off, kWave));
+                        mx[c] = max(mx[c], __shfl_xor(mx[c], off, kWave));
+                    }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    gmn[c] = mn[c];
+                    gE[c] = mx[c] - mn[c] + 1;
+                }
+                tiled = (int64_t)gE[0] * gE[1] * gE[2] <= ACC;
+            }
+            if (tiled) {
+                for (int i = lane; i < gE[0] * gE[1] * gE[2]; i += kWave) acc[i] = OutT(0);
+                __syncthreads();
+            }
+            if (pend[3]) {
+                const double mass = P.m * P.out_scale;
+                if (tiled) {
+                    int li[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const int nca = P.nc[c];
+                        int d = pend[c] - gref[c];
+                        if (2 * d > nca) d -= nca;
+                        else if (2 * d < -nca) d += nca;
+                        li[c] = d - gmn[c];
+                    }
+                    lds_add(acc + (li[0] * gE[1] + li[1]) * gE[2] + li[2], (OutT)mass);
+                } else {
+                    atomicAdd(out + out_index(P, pend[0], pend[1], pend[2]), (OutT)mass);
+                }
+            }
+        }
 
         // Walk the group's tetrahedra in tile batches that fit the D buffer.
         int cur = 0;       // next slot to start
@@ -1232,6 +1330,21 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
                             const int gw = k2 == 0 ? gx : (k2 == 1 ? gy : gz);
                             const int nw = k2 == 0 ? P.nc[0] : (k2 == 1 ? P.nc[1] : P.nc[2]);
                             n_pair += t.tl;
+                            // in the group tile: level 0's cell and the walk axis' stride
+                            int li = 0, lstep = 0;
+                            if (AGG && tiled) {
+                                int lc[3];
+#pragma unroll
+                                for (int c = 0; c < 3; ++c) {
+                                    const int nca = P.nc[c];
+                                    int d = S.lo[c] - gref[c];
+                                    if (2 * d > nca) d -= nca;
+                                    else if (2 * d < -nca) d += nca;
+                                    lc[c] = d - gmn[c] + (k0 == c ? o0 : (k1 == c ? o1 : o2));
+                                }
+                                li = (lc[0] * gE[1] + lc[1]) * gE[2] + lc[2];
+                                lstep = k2 == 0 ? gE[1] * gE[2] : (k2 == 1 ? gE[2] : 1);
+                            }
                             // the cell's mass: (d11 - d01) - (d10 - d00); differences of
                             // values up to 1 carry ~1e-16 noise, which is dropped
                             if (!P.leaf_map) {
@@ -1250,9 +1363,11 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
                                     if (V > 4e-15) {
                                         ++n_nz;
                                         const double mass = P.m * V;
-                                        atomicAdd(po, (OutT)(mass * P.out_scale));
+                                        if (AGG && tiled) lds_add(acc + li, (OutT)(mass * P.out_scale));
+                                        else atomicAdd(po, (OutT)(mass * P.out_scale));
                                         macc += mass;
                                     }
+                                    li += lstep;
                                     po += step;
                                     if (++w == nw) {
                                         w = 0;
@@ -1283,10 +1398,12 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
                                     if (V > 4e-15 && leaf >= 0) {
                                         ++n_nz;
                                         const double mass = P.m * V;
-                                        atomicAdd(out + ((int64_t)leaf * B * B * B + off),
-                                                  (OutT)(mass * P.out_scale));
+                                        if (AGG && tiled) lds_add(acc + li, (OutT)(mass * P.out_scale));
+                                        else atomicAdd(out + ((int64_t)leaf * B * B * B + off),
+                                                       (OutT)(mass * P.out_scale));
                                         macc += mass;
                                     }
+                                    li += lstep;
                                     off += ostep;
                                     if (++rw == B) {
                                         rw = 0;
@@ -1328,6 +1445,27 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
             }
         }
         __syncthreads();
+        if constexpr (AGG) {
+            if (tiled) {
+                // the group tile to the grid: one atomic per non-zero cell
+                const int ncells = gE[0] * gE[1] * gE[2];
+                for (int i = lane; i < ncells; i += kWave) {
+                    const OutT v = acc[i];
+                    if (v == OutT(0)) continue;
+                    const int li[3] = {i / (gE[1] * gE[2]), (i / gE[2]) % gE[1], i % gE[2]};
+                    int g3[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const int nca = P.nc[c];
+                        int x = (gref[c] + gmn[c] + li[c]) % nca;
+                        g3[c] = x < 0 ? x + nca : x;
+                    }
+                    const int64_t idx = out_index(P, g3[0], g3[1], g3[2]);
+                    if (idx >= 0) atomicAdd(out + idx, v);
+                }
+                __syncthreads();
+            }
+        }
         }
     }
     if (cur_box >= 0) flush_mass(P, macc);

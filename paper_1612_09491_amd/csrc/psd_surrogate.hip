@@ -846,6 +846,13 @@ __global__ __launch_bounds__(64, 2) void surrogate_deposit_kernel(UniformArgs P,
     double macc = 0.0;
     unsigned long long n_sur = 0, n_nz = 0, n_inv = 0;
 
+    // After the network, the activation buffer holds the batch's cell masses:
+    // a tile over the union of the n tets' 2x2x2 blocks, flushed with one
+    // global atomic per non-zero cell (the batch's tets come from neighbouring
+    // Lagrangian cubes and share most of their cells).  A batch whose union
+    // is larger than the buffer adds straight to the grid.
+    constexpr int kAcc = (int)(sizeof(hb) / sizeof(OutT));
+    OutT* acc = reinterpret_cast<OutT*>(hb);
     auto run = [&](int n) {
         if (lane < n) {
             const int slot = (head + lane) & (kRing - 1);
@@ -865,6 +872,37 @@ __global__ __launch_bounds__(64, 2) void surrogate_deposit_kernel(UniformArgs P,
         hidden_layer<2, kHS>(hb, hb, nullptr, N.w3, N.w + oB3);
         output_layer(hb, lg, N);
         __syncthreads();
+        // the union box, in cells relative to lane 0's block (minimum image)
+        const int slot0 = head & (kRing - 1);
+        int lo[3], mn[3], mx[3], E[3];
+        {
+            const int slot = (head + (lane < n ? lane : 0)) & (kRing - 1);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int ref = qm[slot0 * 4 + 1 + a], nca = P.nc[a];
+                int d = qm[slot * 4 + 1 + a] - ref;
+                if (2 * d > nca) d -= nca;
+                else if (2 * d < -nca) d += nca;
+                lo[a] = d;
+                mn[a] = d;
+                mx[a] = d;
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    mn[a] = min(mn[a], __shfl_xor(mn[a], off, 64));
+                    mx[a] = max(mx[a], __shfl_xor(mx[a], off, 64));
+                }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) E[a] = mx[a] - mn[a] + 2;
+        }
+        const bool tiled = (int64_t)E[0] * E[1] * E[2] <= kAcc;
+        const int ncell = E[0] * E[1] * E[2];
+        if (tiled) {
+            for (int i = lane; i < ncell; i += 64) acc[i] = OutT(0);
+            __syncthreads();
+        }
         if (lane < n) {
             const int slot = (head + lane) & (kRing - 1);
             const int m = qm[slot * 4] & 0xFF, r = qm[slot * 4] >> 8;
@@ -887,15 +925,41 @@ __global__ __launch_bounds__(64, 2) void surrogate_deposit_kernel(UniformArgs P,
                 const double d = c == last ? P.m - given : (double)p[c] * scale;
                 given += d;
                 if (d == 0.0) continue;
-                const int a = wrap_cell(qm[slot * 4 + 1] + ((c >> 2) & 1), P.nc[0]);
-                const int b = wrap_cell(qm[slot * 4 + 2] + ((c >> 1) & 1), P.nc[1]);
-                const int z = wrap_cell(qm[slot * 4 + 3] + (c & 1), P.nc[2]);
-                atomicAdd(out + ((int64_t)a * P.nc[1] + b) * P.nc[2] + z, (OutT)(d * P.out_scale));
+                if (tiled) {
+                    const int i = ((lo[0] - mn[0] + ((c >> 2) & 1)) * E[1] + (lo[1] - mn[1] + ((c >> 1) & 1))) *
+                                      E[2] + (lo[2] - mn[2] + (c & 1));
+                    __hip_atomic_fetch_add(acc + i, (OutT)(d * P.out_scale), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                } else {
+                    const int a = wrap_cell(qm[slot * 4 + 1] + ((c >> 2) & 1), P.nc[0]);
+                    const int b = wrap_cell(qm[slot * 4 + 2] + ((c >> 1) & 1), P.nc[1]);
+                    const int z = wrap_cell(qm[slot * 4 + 3] + (c & 1), P.nc[2]);
+                    atomicAdd(out + ((int64_t)a * P.nc[1] + b) * P.nc[2] + z, (OutT)(d * P.out_scale));
+                }
                 ++n_nz;
             }
             macc += given;
         }
         __syncthreads();
+        if (tiled) {
+            // one global atomic per non-zero cell of the tile
+            for (int i = lane; i < ncell; i += 64) {
+                const OutT v = acc[i];
+                if (v == OutT(0)) continue;
+                const int i2 = i % E[2], i1 = (i / E[2]) % E[1], i0 = i / (E[1] * E[2]);
+                int g[3];
+                const int li[3] = {i0, i1, i2};
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    int x = qm[slot0 * 4 + 1 + a] + mn[a] + li[a];
+                    const int nca = P.nc[a];
+                    x = x % nca;
+                    g[a] = x < 0 ? x + nca : x;
+                }
+                atomicAdd(out + ((int64_t)g[0] * P.nc[1] + g[1]) * P.nc[2] + g[2], v);
+            }
+            __syncthreads();
+        }
         head = (head + n) & (kRing - 1);
         qn -= n;
     };
