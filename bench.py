@@ -283,8 +283,8 @@ def own_work(pos: np.ndarray, nc, n_cubes: int, cap: int, nz_per_tet: float,
 
 # template arguments after the buffer size of each deposit-kernel instance:
 # tets set up at once, tiles per batch
-GROUP_OF_CAP = {512: "16, 16, 0", 960: "32, 16, 0", 1024: "8, 8, 128", 1408: "8, 8, 0",
-                2048: "32, 32, 0"}
+GROUP_OF_CAP = {512: "16, 16, false, 0", 960: "32, 16, false, 0", 1024: "8, 8, false, 128",
+                1408: "8, 8, false, 0", 2048: "32, 32, false, 0"}
 
 SURROGATE_WEIGHTS = os.path.join(ROOT, "paper_1612_09491_amd", "surrogate_zel256_g64.npy")
 
