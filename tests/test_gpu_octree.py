@@ -130,3 +130,41 @@ def test_clump512_tree_and_sampled_leaves(psd, orc):
     l1 = np.abs(got[sel] - want).sum() / np.abs(want).sum()
     print(f"sampled leaves {sel.tolist()}: L1 {l1:.3e}")
     assert l1 <= 1e-5
+
+
+def test_adaptive_tree_at_scale(psd, orc):
+    """128^3 particles (12.6M tetrahedra) squeezed toward a corner (x -> x^2 per axis over
+    a Zel'dovich grid): with threshold 1e5 the tree has leaves at levels 2, 3 and 4.  The
+    node array is bit-identical to the oracle's; three leaves of every level match the
+    oracle within the FP32 bar; the root's coarse block (internal-node sums) matches the
+    oracle's direct 16^3 deposit."""
+    base = zeldovich_positions(128, 0.5, seed=91).astype(np.float64)
+    pos = (base ** 2).astype(np.float32)
+    kw = dict(block=16, max_level=4, subblock=8, threshold=100000)
+    ref_nodes = orc.build_octree(pos, **kw)
+    pt = _dev(pos)
+    tree = psd.build_octree(pt, **kw)
+    got_nodes = tree.to_numpy()
+    _same_nodes(got_nodes, ref_nodes)
+    leaf_nodes = np.nonzero(ref_nodes["leaf_id"] >= 0)[0]
+    levels = ref_nodes["level"][leaf_nodes]
+    assert set(np.unique(levels).tolist()) == {2, 3, 4}
+    ms = torch.zeros(1, dtype=torch.float64, device=pt.device)
+    out = psd.deposit_octree(pt, tree, mass_sum=ms)
+    torch.cuda.synchronize()
+    assert abs(float(ms.item()) - 1.0) <= 1e-9
+    got = out.double().cpu().numpy()
+    for lvl in (2, 3, 4):
+        sel = leaf_nodes[levels == lvl]
+        ids = ref_nodes["leaf_id"][sel[[0, len(sel) // 2, -1]]]
+        ref, _ = orc.deposit_octree(pos, ref_nodes, ids, block=16)
+        g = got[ids]
+        l1 = np.abs(g - ref).sum() / np.abs(ref).sum()
+        linf = np.abs(g - ref).max() / np.abs(ref).max()
+        print(f"level {lvl} leaves {ids.tolist()}: L1 {l1:.3e} Linf {linf:.3e}", flush=True)
+        assert l1 <= 1e-5 and linf <= 1e-5
+    coarse = psd.octree_coarsen(tree, out).double().cpu().numpy()
+    root_ref, _ = orc.deposit_uniform(pos, 16)
+    l1 = np.abs(coarse[0] - root_ref).sum() / np.abs(root_ref).sum()
+    print(f"root coarse block: L1 {l1:.3e}", flush=True)
+    assert l1 <= 1e-5
