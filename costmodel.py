@@ -160,6 +160,9 @@ def count_events(pos: np.ndarray, nc, cubes: np.ndarray, cap: int = 1024,
     w1 = np.where(w2 == 2, 1, 2)
     axes = np.stack([w0, w1, w2], axis=1)
     vr = np.take_along_axis(V - lo[:, None, :], axes[:, None, :], axis=2)
+    # the kernel keeps each tetrahedron's vertices in increasing walk-frame x
+    # (ties by vertex index), which fixes the triangulation of its pieces
+    vr = np.take_along_axis(vr, np.argsort(vr[:, :, 0], axis=1, kind="stable")[:, :, None], axis=1)
     ex = np.take_along_axis(ext, axes, axis=1)
     for s in range(0, len(vr), batch_tets):
         _count_batch(vr[s:s + batch_tets], ex[s:s + batch_tets], cap, counts)

@@ -39,7 +39,8 @@ namespace {
 // planes, axis 2 gets the exact distribution.  Axis 2 is the longest side of
 // the bbox, which makes the fewest columns for the same cells.
 struct CTet {
-    double vr[4][3];  // vertices relative to the bbox origin, walk-frame axes (cell units), exact
+    double vr[4][3];  // vertices relative to the bbox origin, walk-frame axes (cell units), exact,
+                      // in increasing walk-frame x
     int lo[3];        // bbox origin wrapped into [0, nc), grid axes
     int ext[3];       // bbox extent in cells, walk-frame axes
     int ncell;        // ext0 * ext1 * ext2 (0: nothing to do)
@@ -322,22 +323,19 @@ __device__ __forceinline__ void column(const CTet& S, int a, int b, const Tile& 
 #pragma unroll
         for (int c = 0; c < 3; ++c) v[q][c] = S.vr[q][c];
 
-    // level 1: x <= X (inside when X - x >= 0)
+    // level 1: x <= X (inside when X - x >= 0); the vertices are in
+    // increasing x, so the inside ones come first
     double dx[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) dx[q] = cx ? X - v[q][0] : 1.0;
     Split<double> s1;
-    split_plane(dx, s1);
+    split_prefix(dx, s1);
     if (s1.nin == 0) return;
-    // permuted vertices' (y, z)
     double P1[4][2];
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        P1[0][c] = sel4(v[0][c + 1], v[1][c + 1], v[2][c + 1], v[3][c + 1], s1.ia);
-        P1[1][c] = sel4(v[0][c + 1], v[1][c + 1], v[2][c + 1], v[3][c + 1], s1.ib);
-        P1[2][c] = sel4(v[0][c + 1], v[1][c + 1], v[2][c + 1], v[3][c + 1], s1.ic);
-        P1[3][c] = sel4(v[0][c + 1], v[1][c + 1], v[2][c + 1], v[3][c + 1], s1.id);
-    }
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) P1[q][c] = v[q][c + 1];
     const bool a1 = s1.nin == 1, a2 = s1.nin == 2, a3 = s1.nin == 3, a4 = s1.nin == 4;
     double U0[2], U1[2], U2[2], W0[2], W1[2], W2[2];
 #pragma unroll
@@ -468,16 +466,13 @@ __device__ __forceinline__ void column_queue(bool valid, const CTet& S, int a, i
         double dx[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) dx[q] = cx ? X - v[q][0] : 1.0;
-        split_plane(dx, s1);
+        split_prefix(dx, s1);  // vertices in increasing x: the inside ones first
         if (s1.nin > 0) {
             double P1[4][2];
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                P1[0][c] = sel4(v[0][c + 1], v[1][c + 1], v[2][c + 1], v[3][c + 1], s1.ia);
-                P1[1][c] = sel4(v[0][c + 1], v[1][c + 1], v[2][c + 1], v[3][c + 1], s1.ib);
-                P1[2][c] = sel4(v[0][c + 1], v[1][c + 1], v[2][c + 1], v[3][c + 1], s1.ic);
-                P1[3][c] = sel4(v[0][c + 1], v[1][c + 1], v[2][c + 1], v[3][c + 1], s1.id);
-            }
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) P1[q][c] = v[q][c + 1];
             const bool a1 = s1.nin == 1, a2 = s1.nin == 2, a3 = s1.nin == 3, a4 = s1.nin == 4;
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
@@ -913,6 +908,8 @@ __device__ __forceinline__ int setup_tet(const BoxDesc& P, int64_t tid, CTet& S,
     const int w0 = w2 == 0 ? 1 : 0, w1 = w2 == 2 ? 1 : 2;
     S.axes = w0 | (w1 << 2) | (w2 << 4);
     const int wa[3] = {w0, w1, w2};
+    double w[4][3];
+    int id[4] = {0, 1, 2, 3};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int c = wa[k];
@@ -920,8 +917,31 @@ __device__ __forceinline__ int setup_tet(const BoxDesc& P, int64_t tid, CTet& S,
         S.ext[k] = c == 0 ? e[0] : (c == 1 ? e[1] : e[2]);
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-            S.vr[q][k] = (c == 0 ? T.v[q][0] : (c == 1 ? T.v[q][1] : T.v[q][2])) - lo;
+            w[q][k] = (c == 0 ? T.v[q][0] : (c == 1 ? T.v[q][1] : T.v[q][2])) - lo;
     }
+    // vertices in increasing walk-frame x (ties by vertex index): every
+    // plane x <= a+1 then has its inside vertices first (split_prefix)
+    auto order = [&](int i, int j) {
+        const bool sw = w[i][0] > w[j][0] || (w[i][0] == w[j][0] && id[i] > id[j]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double t = w[i][k];
+            w[i][k] = sw ? w[j][k] : t;
+            w[j][k] = sw ? t : w[j][k];
+        }
+        const int ti = id[i];
+        id[i] = sw ? id[j] : ti;
+        id[j] = sw ? ti : id[j];
+    };
+    order(0, 1);
+    order(2, 3);
+    order(0, 2);
+    order(1, 3);
+    order(1, 2);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) S.vr[q][k] = w[q][k];
     if (ncell == 1) {
         // the tetrahedron lies inside one cell
         ++n_pair;

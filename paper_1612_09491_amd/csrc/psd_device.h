@@ -106,22 +106,11 @@ struct Split {
     R f0, f1, f2;
 };
 
+// Cut parameters and piece fractions from the plane values of the ordered
+// vertices (inside ones first).
 template <typename R>
-__device__ __forceinline__ void split_plane(const R d[4], Split<R>& s)
+__device__ __forceinline__ void split_ordered(R da, R db, R dc, R dd, int nin, Split<R>& s)
 {
-    int mask = (d[0] >= R(0) ? 1 : 0) | (d[1] >= R(0) ? 2 : 0) | (d[2] >= R(0) ? 4 : 0) |
-               (d[3] >= R(0) ? 8 : 0);
-    int nin = __builtin_popcount(mask);
-    uint32_t pc = perm_code(mask);
-    s.nin = nin;
-    s.ia = pc & 3;
-    s.ib = (pc >> 2) & 3;
-    s.ic = (pc >> 4) & 3;
-    s.id = (pc >> 6) & 3;
-    R da = sel4(d[0], d[1], d[2], d[3], s.ia);
-    R db = sel4(d[0], d[1], d[2], d[3], s.ib);
-    R dc = sel4(d[0], d[1], d[2], d[3], s.ic);
-    R dd = sel4(d[0], d[1], d[2], d[3], s.id);
     bool n1 = nin == 1, n2 = nin == 2, n3 = nin == 3;
     R i0 = da, o0 = n1 ? db : (n2 ? dc : dd);
     R i1 = n3 ? db : da, o1 = n1 ? dc : dd;
@@ -148,6 +137,38 @@ __device__ __forceinline__ void split_plane(const R d[4], Split<R>& s)
     s.f0 = f0;
     s.f1 = f1;
     s.f2 = f2;
+}
+
+template <typename R>
+__device__ __forceinline__ void split_plane(const R d[4], Split<R>& s)
+{
+    int mask = (d[0] >= R(0) ? 1 : 0) | (d[1] >= R(0) ? 2 : 0) | (d[2] >= R(0) ? 4 : 0) |
+               (d[3] >= R(0) ? 8 : 0);
+    int nin = __builtin_popcount(mask);
+    uint32_t pc = perm_code(mask);
+    s.nin = nin;
+    s.ia = pc & 3;
+    s.ib = (pc >> 2) & 3;
+    s.ic = (pc >> 4) & 3;
+    s.id = (pc >> 6) & 3;
+    split_ordered(sel4(d[0], d[1], d[2], d[3], s.ia), sel4(d[0], d[1], d[2], d[3], s.ib),
+                  sel4(d[0], d[1], d[2], d[3], s.ic), sel4(d[0], d[1], d[2], d[3], s.id), nin, s);
+}
+
+// The same split when the plane values do not increase with the vertex
+// index (d[0] >= d[1] >= d[2] >= d[3]): the inside vertices are a prefix,
+// already in the order above, so the permutation is the identity.
+template <typename R>
+__device__ __forceinline__ void split_prefix(const R d[4], Split<R>& s)
+{
+    const int nin = (d[0] >= R(0) ? 1 : 0) + (d[1] >= R(0) ? 1 : 0) + (d[2] >= R(0) ? 1 : 0) +
+                    (d[3] >= R(0) ? 1 : 0);
+    s.nin = nin;
+    s.ia = 0;
+    s.ib = 1;
+    s.ic = 2;
+    s.id = 3;
+    split_ordered(d[0], d[1], d[2], d[3], nin, s);
 }
 
 // Plane evaluators.  Planes are compacted per lane so that the k planes that
