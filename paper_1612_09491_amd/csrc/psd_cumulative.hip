@@ -108,7 +108,7 @@ __device__ __forceinline__ int64_t out_index(const BoxDesc& P, int x, int y, int
     if (!P.leaf_map) return ((int64_t)x * P.nc[1] + y) * P.nc[2] + z;
     const int B = P.leaf_block, side = P.leaf_side;
     const int nx = x / B, ny = y / B, nz = z / B;
-    const int leaf = P.leaf_map[(nx * side + ny) * side + nz];
+    const int leaf = global_view(P.leaf_map)[(nx * side + ny) * side + nz];
     if (leaf < 0) return -1;
     return (int64_t)leaf * B * B * B + ((x - nx * B) * B + (y - ny * B)) * B + (z - nz * B);
 }
@@ -129,7 +129,7 @@ __device__ __forceinline__ bool touches_leaf(const BoxDesc& P, const int lo[3], 
         for (int b = 0; b < nn[1]; ++b)
             for (int c = 0; c < nn[2]; ++c) {
                 const int x = (n0[0] + a) % side, y = (n0[1] + b) % side, z = (n0[2] + c) % side;
-                if (P.leaf_map[(x * side + y) * side + z] >= 0) return true;
+                if (global_view(P.leaf_map)[(x * side + y) * side + z] >= 0) return true;
             }
     return false;
 }
@@ -876,7 +876,7 @@ __device__ __forceinline__ int setup_tet(const BoxDesc& P, int64_t tid, CTet& S,
                 pend[2] = g[2];
                 pend[3] = 1;
             } else {
-                atomicAdd(out + idx, (OutT)(P.m * P.out_scale));
+                global_add(out + idx, (OutT)(P.m * P.out_scale));
             }
             macc += P.m;
         }
@@ -954,7 +954,7 @@ __device__ __forceinline__ int setup_tet(const BoxDesc& P, int64_t tid, CTet& S,
                 pend[2] = S.lo[2];
                 pend[3] = 1;
             } else {
-                atomicAdd(out + idx, (OutT)(P.m * P.out_scale));
+                global_add(out + idx, (OutT)(P.m * P.out_scale));
             }
             macc += P.m;
         }
@@ -967,7 +967,7 @@ __device__ __forceinline__ void flush_mass(const BoxDesc& P, double& macc)
 {
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) macc += __shfl_xor(macc, off, kWave);
-    if (threadIdx.x == 0 && P.mass_sum && macc != 0.0) atomicAdd(P.mass_sum, macc);
+    if (threadIdx.x == 0 && P.mass_sum && macc != 0.0) global_add(P.mass_sum, macc);
     macc = 0.0;
 }
 
@@ -1025,14 +1025,14 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
         const int64_t item = s_item;
         __syncthreads();
         if (item >= Q.n_chunks) break;
-        const int64_t g = Q.order ? Q.order[item] : item;
+        const int64_t g = Q.order ? global_view(Q.order)[item] : item;
         const int bi = box_of(Q, g);
         if (bi != cur_box) {
             if (cur_box >= 0) flush_mass(P, macc);
             cur_box = bi;
             if (Q.boxes) P = Q.boxes[bi];
         }
-        if (P.level_has_leaf && *P.level_has_leaf == 0) {
+        if (P.level_has_leaf && *global_view(P.level_has_leaf) == 0) {
             // a level without leaves: in index order its remaining chunks
             // are skipped in one step (the counter only moves forward)
             if (!Q.order && lane == 0) {
@@ -1131,7 +1131,7 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
                     }
                     lds_add(acc + (li[0] * gE[1] + li[1]) * gE[2] + li[2], (OutT)mass);
                 } else {
-                    atomicAdd(out + out_index(P, pend[0], pend[1], pend[2]), (OutT)mass);
+                    global_add(out + out_index(P, pend[0], pend[1], pend[2]), (OutT)mass);
                 }
             }
         }
@@ -1337,10 +1337,15 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
                         if (i >= 0 && j >= 0) {
                             // the slab form holds the cells' own volumes: no differences
                             const bool has_a = !SLAB && (t.a0 + i) > 0, has_b = !SLAB && (t.b0 + j) > 0;
+                            // the lower neighbours' columns; an absent one is read
+                            // from this column and weighted by 0, which gives
+                            // (d11 - d01) - (d10 - d00) with that term 0, bit for bit
                             const DT* D11 = Dbuf + t.doff + r * t.tl;
-                            const DT* D01 = D11 - wb * t.tl;
-                            const DT* D10 = D11 - t.tl;
-                            const DT* D00 = D01 - t.tl;
+                            const DT* D01 = has_a ? D11 - wb * t.tl : D11;
+                            const DT* D10 = has_b ? D11 - t.tl : D11;
+                            const DT* D00 = (has_a && has_b) ? D11 - (wb + 1) * t.tl : D11;
+                            const double ma = has_a ? 1.0 : 0.0, mb = has_b ? 1.0 : 0.0;
+                            const double mab = ma * mb;
                             // grid cell of level 0, and the grid axis the levels walk
                             const int o0 = t.a0 + i, o1 = t.b0 + j, o2 = t.l0;
                             const int k0 = walk_axis(S, 0), k1 = walk_axis(S, 1), k2 = walk_axis(S, 2);
@@ -1375,16 +1380,13 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
                                 OutT* po = out + ((int64_t)gx * P.nc[1] + gy) * P.nc[2] + gz;
                                 int w = gw;
                                 for (int l = 0; l < t.tl; ++l) {
-                                    const double d11 = D11[l];
-                                    const double d01 = has_a ? D01[l] : 0.0;
-                                    const double d10 = has_b ? D10[l] : 0.0;
-                                    const double d00 = (has_a && has_b) ? D00[l] : 0.0;
-                                    const double V = (d11 - d01) - (d10 - d00);
+                                    const double V = fma(-ma, (double)D01[l], (double)D11[l]) -
+                                                     fma(-mab, (double)D00[l], mb * (double)D10[l]);
                                     if (V > 4e-15) {
                                         ++n_nz;
                                         const double mass = P.m * V;
                                         if (AGG && tiled) lds_add(acc + li, (OutT)(mass * P.out_scale));
-                                        else atomicAdd(po, (OutT)(mass * P.out_scale));
+                                        else global_add(po, (OutT)(mass * P.out_scale));
                                         macc += mass;
                                     }
                                     li += lstep;
@@ -1408,19 +1410,16 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
                                 const int nstep = k2 == 0 ? side * side : (k2 == 1 ? side : 1);
                                 int rw = k2 == 0 ? rx : (k2 == 1 ? ry : rz);
                                 int qw = k2 == 0 ? cx : (k2 == 1 ? cy : cz);
-                                int leaf = P.leaf_map[node];
+                                int leaf = global_view(P.leaf_map)[node];
                                 for (int l = 0; l < t.tl; ++l) {
-                                    const double d11 = D11[l];
-                                    const double d01 = has_a ? D01[l] : 0.0;
-                                    const double d10 = has_b ? D10[l] : 0.0;
-                                    const double d00 = (has_a && has_b) ? D00[l] : 0.0;
-                                    const double V = (d11 - d01) - (d10 - d00);
+                                    const double V = fma(-ma, (double)D01[l], (double)D11[l]) -
+                                                     fma(-mab, (double)D00[l], mb * (double)D10[l]);
                                     if (V > 4e-15 && leaf >= 0) {
                                         ++n_nz;
                                         const double mass = P.m * V;
                                         if (AGG && tiled) lds_add(acc + li, (OutT)(mass * P.out_scale));
-                                        else atomicAdd(out + ((int64_t)leaf * B * B * B + off),
-                                                       (OutT)(mass * P.out_scale));
+                                        else global_add(out + ((int64_t)leaf * B * B * B + off),
+                                                        (OutT)(mass * P.out_scale));
                                         macc += mass;
                                     }
                                     li += lstep;
@@ -1433,18 +1432,15 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
                                             qw = 0;
                                             node -= side * nstep;
                                         }
-                                        leaf = P.leaf_map[node];
+                                        leaf = global_view(P.leaf_map)[node];
                                     }
                                 }
                             } else {
                                 // octree level (large-tet instances, which have no
                                 // registers to spare): each non-zero cell mapped alone
                                 for (int l = 0; l < t.tl; ++l) {
-                                    const double d11 = D11[l];
-                                    const double d01 = has_a ? D01[l] : 0.0;
-                                    const double d10 = has_b ? D10[l] : 0.0;
-                                    const double d00 = (has_a && has_b) ? D00[l] : 0.0;
-                                    const double V = (d11 - d01) - (d10 - d00);
+                                    const double V = fma(-ma, (double)D01[l], (double)D11[l]) -
+                                                     fma(-mab, (double)D00[l], mb * (double)D10[l]);
                                     if (V > 4e-15) {
                                         const int w = wrap_add(gw, l, nw);
                                         const int64_t gi = out_index(P, k2 == 0 ? w : gx,
@@ -1452,7 +1448,7 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
                                         if (gi >= 0) {
                                             ++n_nz;
                                             const double mass = P.m * V;
-                                            atomicAdd(out + gi, (OutT)(mass * P.out_scale));
+                                            global_add(out + gi, (OutT)(mass * P.out_scale));
                                             macc += mass;
                                         }
                                     }
@@ -1481,7 +1477,7 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
                         g3[c] = x < 0 ? x + nca : x;
                     }
                     const int64_t idx = out_index(P, g3[0], g3[1], g3[2]);
-                    if (idx >= 0) atomicAdd(out + idx, v);
+                    if (idx >= 0) global_add(out + idx, v);
                 }
                 __syncthreads();
             }

@@ -31,6 +31,22 @@ __device__ __forceinline__ R sel4(R a0, R a1, R a2, R a3, int i)
     return (i & 2) ? hi : lo;
 }
 
+// Global-memory views of generic pointers: loads and atomics through them
+// compile to global instructions rather than flat ones, which the hardware
+// also counts as LDS accesses (every wait on the wavefront's LDS reads then
+// waits for them too).
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* global_view(const T* p)
+{
+    return (const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ void global_add(T* p, T v)
+{
+    __hip_atomic_fetch_add((__attribute__((address_space(1))) T*)p, v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Quotient a / b for b > 0 with a few ulps of error (the FP64 reciprocal
 // estimate refined by one Newton step, which doubles its correct bits).
 __device__ __forceinline__ float fdiv_pos(float a, float b)
@@ -291,10 +307,11 @@ __device__ __forceinline__ void make_tet(const float* __restrict__ pos, int np0,
         if (ii == np0) ii = 0;
         if (jj == np1) jj = 0;
         if (kk == np2) kk = 0;
-        const float* pp = pos + 3 * ((ii * np1 + jj) * np2 + kk);
-        c[m][0] = (double)__ldg(pp + 0) * sc[0];
-        c[m][1] = (double)__ldg(pp + 1) * sc[1];
-        c[m][2] = (double)__ldg(pp + 2) * sc[2];
+        const __attribute__((address_space(1))) float* pp =
+            global_view(pos) + 3 * ((ii * np1 + jj) * np2 + kk);
+        c[m][0] = (double)pp[0] * sc[0];
+        c[m][1] = (double)pp[1] * sc[1];
+        c[m][2] = (double)pp[2] * sc[2];
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
