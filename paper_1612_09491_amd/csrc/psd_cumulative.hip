@@ -56,13 +56,12 @@ struct Tile {
     int a0, ta, b0, tb, l0, tl;
     int ha, hb;
     int doff;        // offset in the D buffer
-    float inv_wb;    // 1 / (tb + hb)
-    float inv_tb;    // 1 / tb
-    float inv_tl;    // 1 / tl
+    float inv_wb;    // 1 / (tb + hb), the hardware reciprocal (fdivi's bound holds for it)
 };
 
-// q = n / d for 0 <= n < 2^20 via a float reciprocal (exact in that range:
-// the error of (n + 1/2) * (1/d) stays below 1/(2d)).
+// q = n / d for 0 <= n < 2^20 via a float reciprocal of relative error up to
+// 2^-23 (the hardware's): (n + 1/2) * inv_d is off from (n + 1/2) / d by less
+// than (n + 1/2) * 1.8e-7 / d < 1/(2d), so it stays inside (q, q + 1).
 __device__ __forceinline__ int fdivi(int n, float inv_d)
 {
     return (int)(((float)n + 0.5f) * inv_d);
@@ -1171,9 +1170,7 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
                             t.a0 = 0; t.ta = S.ext[0]; t.b0 = 0; t.tb = S.ext[1];
                             t.l0 = 0; t.tl = S.ext[2]; t.ha = 0; t.hb = 0;
                             t.doff = used + incl - ds;
-                            t.inv_wb = 1.0f / (float)t.tb;
-                            t.inv_tb = t.inv_wb;
-                            t.inv_tl = 1.0f / (float)t.tl;
+                            t.inv_wb = __builtin_amdgcn_rcpf((float)t.tb);
                             tiles[nt + rank - 1] = t;
                             t_slot[nt + rank - 1] = s;
                         }
@@ -1219,9 +1216,7 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
                     rows += t.ta;
                 }
                 t.doff = used;
-                t.inv_wb = 1.0f / (float)(t.tb + t.hb);
-                t.inv_tb = 1.0f / (float)t.tb;
-                t.inv_tl = 1.0f / (float)t.tl;
+                t.inv_wb = __builtin_amdgcn_rcpf((float)(t.tb + t.hb));
                 used += ds;
                 if (lane == 0) {
                     tiles[nt] = t;
