@@ -851,7 +851,7 @@ __global__ __launch_bounds__(64, 2) void surrogate_deposit_kernel(UniformArgs P,
     // global atomic per non-zero cell (the batch's tets come from neighbouring
     // Lagrangian cubes and share most of their cells).  A batch whose union
     // is larger than the buffer adds straight to the grid.
-    constexpr int kAcc = (int)(sizeof(hb) / sizeof(OutT));
+    constexpr int kAcc = (int)(sizeof(hb) / (sizeof(OutT)));  // OutT entries in the bytes of hb
     OutT* acc = reinterpret_cast<OutT*>(hb);
     auto run = [&](int n) {
         if (lane < n) {
@@ -934,7 +934,7 @@ __global__ __launch_bounds__(64, 2) void surrogate_deposit_kernel(UniformArgs P,
                     const int a = wrap_cell(qm[slot * 4 + 1] + ((c >> 2) & 1), P.nc[0]);
                     const int b = wrap_cell(qm[slot * 4 + 2] + ((c >> 1) & 1), P.nc[1]);
                     const int z = wrap_cell(qm[slot * 4 + 3] + (c & 1), P.nc[2]);
-                    atomicAdd(out + ((int64_t)a * P.nc[1] + b) * P.nc[2] + z, (OutT)(d * P.out_scale));
+                    global_add(out + ((int64_t)a * P.nc[1] + b) * P.nc[2] + z, (OutT)(d * P.out_scale));
                 }
                 ++n_nz;
             }
@@ -956,7 +956,7 @@ __global__ __launch_bounds__(64, 2) void surrogate_deposit_kernel(UniformArgs P,
                     x = x % nca;
                     g[a] = x < 0 ? x + nca : x;
                 }
-                atomicAdd(out + ((int64_t)g[0] * P.nc[1] + g[1]) * P.nc[2] + g[2], v);
+                global_add(out + ((int64_t)g[0] * P.nc[1] + g[1]) * P.nc[2] + g[2], v);
             }
             __syncthreads();
         }
@@ -1013,7 +1013,7 @@ __global__ __launch_bounds__(64, 2) void surrogate_deposit_kernel(UniformArgs P,
     if (qn > 0) run(qn);
 
     macc = wave_sum(macc);
-    if (lane == 0 && P.mass_sum && macc != 0.0) atomicAdd(P.mass_sum, macc);
+    if (lane == 0 && P.mass_sum && macc != 0.0) global_add(P.mass_sum, macc);
     if (P.stats) {
         unsigned long long a = n_sur, b = n_nz, c = n_inv;
 #pragma unroll

@@ -45,7 +45,7 @@ __device__ __forceinline__ void scatter(OutT* out, const UniformArgs& P, int a, 
 {
     int64_t idx = ((int64_t)a * P.nc[1] + b) * P.nc[2] + c;
     OutT val = (OutT)(mass * P.out_scale);
-    atomicAdd(out + idx, val);
+    global_add(out + idx, val);
     acc += mass;
 }
 
@@ -406,7 +406,7 @@ __global__ __launch_bounds__(kWave) void deposit_uniform_kernel(UniformArgs P)
         n_deg += __shfl_xor(n_deg, off, kWave);
     }
     if (lane == 0) {
-        if (P.mass_sum) atomicAdd(P.mass_sum, macc);
+        if (P.mass_sum) global_add(P.mass_sum, macc);
         if (P.stats) {
             atomicAdd(P.stats + 0, n_tet);
             atomicAdd(P.stats + 1, n_pair);
