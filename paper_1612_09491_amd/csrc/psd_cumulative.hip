@@ -396,6 +396,16 @@ __device__ __forceinline__ void column(const CTet& S, int a, int b, const Tile& 
 }
 
 
+// Orders a wavefront's LDS accesses before the ones that follow: they
+// complete in issue order, so a wavefront fence (no wait on the global atomics
+// in flight) is enough for values other lanes wrote.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Pieces of the two-plane splits waiting for their z walk: a ring of QCAP
 // records in LDS (QCAP a power of two), one per piece: its four vertex
 // heights, its volume fraction of the tetrahedron, and where its levels go
@@ -417,12 +427,7 @@ __device__ __forceinline__ void drain_round(PieceRing<QCAP, R>& Q, int& head, in
                                             const Tile* tiles, R* Dbuf, WorkCount& wc,
                                             bool local_z = false)
 {
-    // the ring's records were written by other lanes of this wavefront: its
-    // LDS accesses complete in issue order, so a wavefront fence (no wait on
-    // the global atomics in flight) orders them
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_lds_sync();  // the ring's records were written by other lanes
     const int lane = threadIdx.x;
     const int ntake = count < kWave ? count : kWave;
     if (lane < ntake) {
@@ -438,8 +443,8 @@ __device__ __forceinline__ void drain_round(PieceRing<QCAP, R>& Q, int& head, in
 }
 
 // Column (a,b) of one tile (valid lanes only; every lane of the wavefront
-// calls it): zeroes the D column, splits T by x <= a+1 and y <= b+1 as
-// column() does, and queues the pieces; full rounds of 64 are walked as they
+// calls it; the D column is zeroed with the batch's): splits T by x <= a+1
+// and y <= b+1 as column() does, and queues the pieces; full rounds of 64 are walked as they
 // fill.  Loops run to the wavefront's largest piece count, so that the
 // rounds are taken with every lane present.
 template <bool WORK, int QCAP>
@@ -452,9 +457,7 @@ __device__ __forceinline__ void column_queue(bool valid, const CTet& S, int a, i
     int n1 = 0;
     Split<double> s1;
     double U0[2], U1[2], U2[2], W0[2], W1[2], W2[2];
-    if (valid) {
-        double* Dcol = Dbuf + doff;
-        for (int l = 0; l < t.tl; ++l) Dcol[l] = 0.0;
+    if (valid) {  // the batch's D columns were zeroed before its first window
         const bool cx = a + 1 < S.ext[0];
         const double X = (double)(a + 1);
         double v[4][3];
@@ -993,7 +996,7 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
     using DT = typename std::conditional<SLAB, float, double>::type;
     constexpr int SLAB_ROWS = SLAB ? 16 : 1;
     __shared__ CTet slots[GROUP];
-    __shared__ DT Dbuf[CAP];
+    __shared__ __attribute__((aligned(16))) DT Dbuf[CAP];
     __shared__ Tile tiles[TILES];
     __shared__ int t_slot[TILES];
     __shared__ int64_t s_incl[TILES];
@@ -1271,6 +1274,13 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
                     }
                     __syncthreads();
                 }
+                if constexpr (QCAP > 0 && !SLAB) {
+                    // the batch's D columns (used entries) zeroed by all lanes
+                    // at once, two entries a lane per store
+                    double2* Z = reinterpret_cast<double2*>(Dbuf);
+                    for (int i = lane; 2 * i < used; i += kWave) Z[i] = make_double2(0.0, 0.0);
+                    wave_lds_sync();
+                }
                 if constexpr (QCAP > 0) {
                     // Phase 1 for every window of the batch, the pieces of all
                     // columns walked 64 at a time; phase 2 follows once the
@@ -1369,12 +1379,13 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
                             // values up to 1 carry ~1e-16 noise, which is dropped
                             if (!P.leaf_map) {
                                 // plain grid: the element of level 0, then one stride of
-                                // the walk axis per level, nw strides back at the wrap
+                                // the walk axis per level; the levels from lw on lie
+                                // past the periodic wrap, nw strides back (a second
+                                // loop, empty for nearly every column)
                                 const int64_t step = k2 == 0 ? (int64_t)P.nc[1] * P.nc[2]
                                                              : (k2 == 1 ? (int64_t)P.nc[2] : 1);
                                 OutT* po = out + ((int64_t)gx * P.nc[1] + gy) * P.nc[2] + gz;
-                                int w = gw;
-                                for (int l = 0; l < t.tl; ++l) {
+                                auto cell = [&](int l) {
                                     const double V = fma(-ma, (double)D01[l], (double)D11[l]) -
                                                      fma(-mab, (double)D00[l], mb * (double)D10[l]);
                                     if (V > 4e-15) {
@@ -1386,11 +1397,11 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
                                     }
                                     li += lstep;
                                     po += step;
-                                    if (++w == nw) {
-                                        w = 0;
-                                        po -= step * nw;
-                                    }
-                                }
+                                };
+                                const int lw = min(t.tl, nw - gw);
+                                for (int l = 0; l < lw; ++l) cell(l);
+                                po -= step * nw;
+                                for (int l = lw; l < t.tl; ++l) cell(l);
                             } else if constexpr (CAP <= 960) {
                                 // octree level (the instances for small tets): the node
                                 // and in-leaf offset of level 0, then one cell of the
