@@ -1141,6 +1141,10 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
         // Walk the group's tetrahedra in tile batches that fit the D buffer.
         int cur = 0;       // next slot to start
         int cur_tile = 0;  // for a tiled tetrahedron, linear index of its next tile
+        // a tiled tetrahedron's tile shape (set at its first tile) and the
+        // position (ix, iy, iz) of tile cur_tile in its nx * ny * nz grid
+        int sh_ta = 1, sh_tb = 1, sh_tl = 1, sh_nx = 1, sh_ny = 1, sh_n = 1;
+        int ix = 0, iy = 0, iz = 0;
         while (cur < GROUP) {
             // Wave-uniform planning (every lane computes the same list).
             // With 16-tet groups (small tets, many per batch) runs of
@@ -1198,14 +1202,17 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
                     t.a0 = 0; t.ta = S.ext[0]; t.b0 = 0; t.tb = S.ext[1];
                     t.l0 = 0; t.tl = S.ext[2]; t.ha = 0; t.hb = 0;
                 } else {
-                    int ta, tb, tl;
-                    if constexpr (SLAB) tile_shape_slab<CAP>(S, SLAB_ROWS, ta, tb, tl, ntiles);
-                    else tile_shape<CAP>(S, ta, tb, tl, ntiles);
-                    const int nx = (S.ext[0] + ta - 1) / ta, ny = (S.ext[1] + tb - 1) / tb;
-                    const int ix = cur_tile % nx, iy = (cur_tile / nx) % ny, iz = cur_tile / (nx * ny);
-                    t.a0 = ix * ta; t.ta = min(ta, S.ext[0] - t.a0);
-                    t.b0 = iy * tb; t.tb = min(tb, S.ext[1] - t.b0);
-                    t.l0 = iz * tl; t.tl = min(tl, S.ext[2] - t.l0);
+                    if (cur_tile == 0) {
+                        if constexpr (SLAB) tile_shape_slab<CAP>(S, SLAB_ROWS, sh_ta, sh_tb, sh_tl, sh_n);
+                        else tile_shape<CAP>(S, sh_ta, sh_tb, sh_tl, sh_n);
+                        sh_nx = (S.ext[0] + sh_ta - 1) / sh_ta;
+                        sh_ny = (S.ext[1] + sh_tb - 1) / sh_tb;
+                        ix = iy = iz = 0;
+                    }
+                    ntiles = sh_n;
+                    t.a0 = ix * sh_ta; t.ta = min(sh_ta, S.ext[0] - t.a0);
+                    t.b0 = iy * sh_tb; t.tb = min(sh_tb, S.ext[1] - t.b0);
+                    t.l0 = iz * sh_tl; t.tl = min(sh_tl, S.ext[2] - t.l0);
                     // the cumulative walk differences against the neighbour
                     // column below; the slab form needs none
                     t.ha = (!SLAB && t.a0 > 0) ? 1 : 0;
@@ -1229,6 +1236,12 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
                 if (++cur_tile >= ntiles) {
                     ++cur;
                     cur_tile = 0;
+                } else if (++ix == sh_nx) {  // the next tile: x fastest, then y, then z
+                    ix = 0;
+                    if (++iy == sh_ny) {
+                        iy = 0;
+                        ++iz;
+                    }
                 }
             }
             __syncthreads();
