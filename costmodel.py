@@ -35,7 +35,11 @@ oracle's counting mode, reported beside it as an equivalent rate).  ``count_even
 replays the kernel's geometry on a sample of Lagrangian cubes in float64 numpy: the
 same unwrap, bbox, walk frame, tiling of large tetrahedra and piece triangulation, so
 its counts agree with the kernel's work counters except where rounding decides an
-on-plane vertex.  This module is measurement code: it shares no code with the kernels
+on-plane vertex.  The instance with the piece ring (1024 entries) walks the complement where a split
+leaves three vertices inside: for y, the x-piece whole and minus its one outside
+tetrahedron (two pieces instead of three); for x, when the tile holds the bbox's last
+row, minus the one outside tetrahedron (its D column then gets the last row's added).
+This module is measurement code: it shares no code with the kernels
 or with the oracle.
 """
 
@@ -127,6 +131,11 @@ def _split(V: np.ndarray, d: np.ndarray):
     return np.concatenate(out), np.concatenate(parent)
 
 
+# buffer sizes of the instances that walk their pieces through the ring, where the
+# splits that leave three vertices inside take the complement
+RING_CAPS = (1024,)
+
+
 def _tile_shape(ext, cap):
     tl = min(ext[2], cap // 4)
     tb = min(ext[1], cap // (2 * tl) - 1)
@@ -171,7 +180,7 @@ def count_events(pos: np.ndarray, nc, cubes: np.ndarray, cap: int = 1024,
 
 def _count_batch(vr, ex, cap, counts):
     # columns of every tile: (tet, a, b, l0, tl, halo)
-    T, A, B, L0, TL, HALO = [], [], [], [], [], []
+    T, A, B, L0, TL, HALO, LAST = [], [], [], [], [], [], []
     for t in range(len(vr)):
         e = [int(x) for x in ex[t]]
         if e[0] * e[1] * e[2] <= cap:
@@ -192,20 +201,55 @@ def _count_batch(vr, ex, cap, counts):
             L0.append(np.full(n, l0))
             TL.append(np.full(n, tl))
             HALO.append(((aa < a0) | (bb < b0)).ravel())
+            LAST.append(np.full(n, a0 + ta == e[0]))
     T, A, B = np.concatenate(T), np.concatenate(A), np.concatenate(B)
     L0, TL, HALO = np.concatenate(L0), np.concatenate(TL), np.concatenate(HALO)
+    LAST = np.concatenate(LAST)
     counts["column"] += int(T.size)
     counts["colcell"] += int(TL.sum())
     verts = vr[T]                                           # [c, 4, 3]
     X = (A + 1).astype(np.float64)
     cx = (A + 1) < ex[T, 0]
     dx = np.where(cx[:, None], X[:, None] - verts[:, :, 0], 1.0)
-    P1, par1 = _split(verts[:, :, 1:], dx)                   # carry (y, z)
+    ring = cap in RING_CAPS
+    if ring:
+        # the x complement: three vertices inside x <= a+1 (vertices in increasing x)
+        # and the tile holding the bbox's last row -> the one outside tetrahedron
+        cmp = cx & (dx[:, 2] >= 0) & (dx[:, 3] < 0) & LAST
+        Pa, para = _split(verts[~cmp][:, :, 1:], dx[~cmp])
+        vc = verts[cmp]
+        d3 = vc[:, 3, 0] - X[cmp]
+        pts = [vc[:, 3]]
+        for q in range(3):
+            t = d3 / (d3 - (vc[:, q, 0] - X[cmp]))
+            pts.append(vc[:, 3] + t[:, None] * (vc[:, q] - vc[:, 3]))
+        P1 = np.concatenate([Pa, np.stack(pts, axis=1)[:, :, 1:]])
+        par1 = np.concatenate([np.flatnonzero(~cmp)[para], np.flatnonzero(cmp)])
+    else:
+        P1, par1 = _split(verts[:, :, 1:], dx)               # carry (y, z)
     counts["xpiece"] += int(len(P1))
     Y = (B[par1] + 1).astype(np.float64)
     cy = (B[par1] + 1) < ex[T[par1], 1]
     dy = np.where(cy[:, None], Y[:, None] - P1[:, :, 0], 1.0)
-    P2, par2 = _split(P1[:, :, 1:], dy)                      # carry z
+    if ring:
+        # the y complement: three vertices inside y <= b+1 -> the x-piece whole and its
+        # one outside tetrahedron (cut points from the inside vertices toward it)
+        three = (dy >= 0).sum(axis=1) == 3
+        Pb, parb = _split(P1[~three][:, :, 1:], dy[~three])
+        Q = P1[three]
+        dq = dy[three]
+        perm = np.argsort(dq < 0, axis=1, kind="stable")     # inside first, then the outside one
+        Qp = np.take_along_axis(Q, perm[:, :, None], axis=1)
+        dp = np.take_along_axis(dq, perm, axis=1)
+        out = [Qp[:, 3]]
+        for q in range(3):
+            t = dp[:, q] / (dp[:, q] - dp[:, 3])
+            out.append(Qp[:, q] + t[:, None] * (Qp[:, 3] - Qp[:, q]))
+        idx3 = np.flatnonzero(three)
+        P2 = np.concatenate([Pb, Q[:, :, 1:], np.stack(out, axis=1)[:, :, 1:]])
+        par2 = np.concatenate([np.flatnonzero(~three)[parb], idx3, idx3])
+    else:
+        P2, par2 = _split(P1[:, :, 1:], dy)                  # carry z
     counts["piece"] += int(len(P2))
     col = par1[par2]
     z = P2[:, :, 0]

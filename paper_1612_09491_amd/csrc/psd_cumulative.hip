@@ -442,11 +442,29 @@ __device__ __forceinline__ void drain_round(PieceRing<QCAP, R>& Q, int& head, in
     count -= ntake;
 }
 
+// Whether column row a of tile t takes the complement of the x split: T has
+// three vertices with x <= a+1 (the vertices are in increasing x), so the
+// inside part is a prism of three pieces while the outside part x > a+1 is
+// one tetrahedron, and the tile holds the bbox's last row, whose D columns
+// are all of T below y = b+1 (no x plane cuts there).  Such a column is
+// walked as minus the outside tetrahedron, and the last row's column is added
+// to it once the walk is done (cumulative_add_last).
+__device__ __forceinline__ bool x_complement(const CTet& S, const Tile& t, int a)
+{
+    const double X = (double)(a + 1);
+    return a + 1 < S.ext[0] && X - S.vr[2][0] >= 0.0 && X - S.vr[3][0] < 0.0 &&
+           t.a0 + t.ta == S.ext[0];
+}
+
 // Column (a,b) of one tile (valid lanes only; every lane of the wavefront
 // calls it; the D column is zeroed with the batch's): splits T by x <= a+1
-// and y <= b+1 as column() does, and queues the pieces; full rounds of 64 are walked as they
-// fill.  Loops run to the wavefront's largest piece count, so that the
-// rounds are taken with every lane present.
+// and y <= b+1 as column() does, and queues the pieces; full rounds of 64 are
+// walked as they fill.  Where a split leaves three vertices inside, the
+// complement is walked instead (Section 6.3's inside-mask split, read from
+// the outside): for y, the whole x-piece plus minus its one outside
+// tetrahedron (two pieces, not three); for x, see x_complement.  Loops run to
+// the wavefront's largest piece count, so that the rounds are taken with
+// every lane present.
 template <bool WORK, int QCAP>
 __device__ __forceinline__ void column_queue(bool valid, const CTet& S, int a, int b, const Tile& t,
                                              int tile_idx, int doff, double* Dbuf,
@@ -457,6 +475,7 @@ __device__ __forceinline__ void column_queue(bool valid, const CTet& S, int a, i
     int n1 = 0;
     Split<double> s1;
     double U0[2], U1[2], U2[2], W0[2], W1[2], W2[2];
+    double xsign = 1.0;
     if (valid) {  // the batch's D columns were zeroed before its first window
         const bool cx = a + 1 < S.ext[0];
         const double X = (double)(a + 1);
@@ -468,13 +487,31 @@ __device__ __forceinline__ void column_queue(bool valid, const CTet& S, int a, i
         double dx[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) dx[q] = cx ? X - v[q][0] : 1.0;
-        split_prefix(dx, s1);  // vertices in increasing x: the inside ones first
+        const int nin = (dx[0] >= 0.0 ? 1 : 0) + (dx[1] >= 0.0 ? 1 : 0) + (dx[2] >= 0.0 ? 1 : 0) +
+                        (dx[3] >= 0.0 ? 1 : 0);
+        // the complement: vertex 3 alone inside x >= X (its value x - X > 0;
+        // the others' are <= 0, a vertex on the plane cut at itself)
+        const bool cmp = x_complement(S, t, a);
+        double d[4], P1[4][2];
+        d[0] = cmp ? -dx[3] : dx[0];
+        d[1] = cmp ? -dx[0] : dx[1];
+        d[2] = cmp ? -dx[1] : dx[2];
+        d[3] = cmp ? -dx[2] : dx[3];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            P1[0][c] = cmp ? v[3][c + 1] : v[0][c + 1];
+            P1[1][c] = cmp ? v[0][c + 1] : v[1][c + 1];
+            P1[2][c] = cmp ? v[1][c + 1] : v[2][c + 1];
+            P1[3][c] = cmp ? v[2][c + 1] : v[3][c + 1];
+        }
+        xsign = cmp ? -1.0 : 1.0;
+        s1.nin = cmp ? 1 : nin;
+        s1.ia = 0;
+        s1.ib = 1;
+        s1.ic = 2;
+        s1.id = 3;
+        split_ordered(d[0], d[1], d[2], d[3], s1.nin, s1);
         if (s1.nin > 0) {
-            double P1[4][2];
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int c = 0; c < 2; ++c) P1[q][c] = v[q][c + 1];
             const bool a1 = s1.nin == 1, a2 = s1.nin == 2, a3 = s1.nin == 3, a4 = s1.nin == 4;
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
@@ -503,7 +540,8 @@ __device__ __forceinline__ void column_queue(bool valid, const CTet& S, int a, i
     for (int j = 0; j < nj; ++j) {
         int n2 = 0;
         Split<double> s2;
-        double u0 = 0.0, u1 = 0.0, u2 = 0.0, w0 = 0.0, w1 = 0.0, w2 = 0.0, f1 = 0.0;
+        double u0 = 0.0, u1 = 0.0, u2 = 0.0, w0 = 0.0, w1 = 0.0, w2 = 0.0, e = 0.0, f1 = 0.0;
+        bool ycmp = false;
         if (j < n1) {
             double cv[4][2];
 #pragma unroll
@@ -513,7 +551,7 @@ __device__ __forceinline__ void column_queue(bool valid, const CTet& S, int a, i
                 cv[2][c] = j == 0 ? U2[c] : W1[c];
                 cv[3][c] = W2[c];
             }
-            f1 = j == 0 ? s1.f0 : (j == 1 ? s1.f1 : s1.f2);
+            f1 = xsign * (j == 0 ? s1.f0 : (j == 1 ? s1.f1 : s1.f2));
             double dy[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) dy[q] = cy ? Y - cv[q][0] : 1.0;
@@ -536,20 +574,30 @@ __device__ __forceinline__ void column_queue(bool valid, const CTet& S, int a, i
                 w0 = b2 ? zb : c0;
                 w1 = b2 ? c2 : c1;
                 w2 = b4 ? zd : (b2 ? c3 : c2);
-                n2 = (b2 || b3) ? 3 : 1;
+                e = zd;
+                // three inside: the x-piece (za, zb, zc, zd) whole, then minus
+                // the outside tetrahedron (zd, c0, c1, c2), whose edges from zd
+                // keep 1 - t of the parent's
+                ycmp = b3;
+                if (b3) {
+                    s2.f0 = 1.0;
+                    s2.f1 = -((1.0 - s2.t0) * (1.0 - s2.t1) * (1.0 - s2.t2));
+                }
+                n2 = b2 ? 3 : (b3 ? 2 : 1);
                 if constexpr (WORK) wc.piece += (unsigned long long)n2;
             }
         }
-        const int nk = __ballot(n2 == 3) ? 3 : (__ballot(n2 == 1) ? 1 : 0);
+        const int nk = __ballot(n2 == 3) ? 3 : (__ballot(n2 == 2) ? 2 : (__ballot(n2 == 1) ? 1 : 0));
         for (int k = 0; k < nk; ++k) {
             const bool has = k < n2;
             const uint64_t bal = __ballot(has);
             if (has) {
                 const int q = (head + count + __popcll(bal & below)) & (QCAP - 1);
-                Q.z[0][q] = u0;
-                Q.z[1][q] = k == 2 ? w0 : u1;
+                const bool c1k = ycmp && k == 1;
+                Q.z[0][q] = c1k ? e : u0;
+                Q.z[1][q] = (k == 2 || c1k) ? w0 : u1;
                 Q.z[2][q] = k == 0 ? u2 : w1;
-                Q.z[3][q] = w2;
+                Q.z[3][q] = (ycmp && k == 0) ? e : w2;
                 Q.frac[q] = f1 * (k == 0 ? s2.f0 : (k == 1 ? s2.f1 : s2.f2));
                 Q.where[q] = (doff << 8) | tile_idx;
             }
@@ -557,6 +605,21 @@ __device__ __forceinline__ void column_queue(bool valid, const CTet& S, int a, i
             if (count >= kWave) drain_round<WORK, QCAP, double>(Q, head, count, tiles, Dbuf, wc);
         }
     }
+}
+
+// After the walk of a batch: every column that took the x complement gets
+// the D column of its tile's last row (same b) added, level by level, which
+// makes it T's D column below y = b+1 minus the outside part's.
+__device__ __forceinline__ void cumulative_add_last(const CTet& S, const Tile& t, int r, double* Dbuf)
+{
+    const int wb = t.tb + t.hb;
+    const int qa = fdivi(r, t.inv_wb);
+    const int a = t.a0 - t.ha + qa;
+    if (!x_complement(S, t, a)) return;
+    const int qlast = t.ta + t.ha - 1;  // the last row of the tile (no x cut there)
+    double* Dcol = Dbuf + t.doff + r * t.tl;
+    const double* Dl = Dbuf + t.doff + (r + (qlast - qa) * wb) * t.tl;
+    for (int l = 0; l < t.tl; ++l) Dcol[l] += Dl[l];
 }
 
 // ---------------------------------------------------------------------------
@@ -1325,6 +1388,17 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
                     while (count > 0)
                         drain_round<WORK, QCAP, DT>(ring, head, count, tiles, Dbuf, wc, SLAB);
                     __syncthreads();
+                    if constexpr (!SLAB) {
+                        for (int64_t base = 0; base < total; base += kWave) {
+                            const int64_t idx = base + lane;
+                            if (idx < total) {
+                                int lo = 0, r = 0;
+                                locate(idx, lo, r);
+                                cumulative_add_last(slots[t_slot[lo]], tiles[lo], r, Dbuf);
+                            }
+                        }
+                        __syncthreads();
+                    }
                 }
                 for (int64_t base = 0; base < total; base += kWave) {
                     const int64_t idx = base + lane;
