@@ -35,10 +35,10 @@ oracle's counting mode, reported beside it as an equivalent rate).  ``count_even
 replays the kernel's geometry on a sample of Lagrangian cubes in float64 numpy: the
 same unwrap, bbox, walk frame, tiling of large tetrahedra and piece triangulation, so
 its counts agree with the kernel's work counters except where rounding decides an
-on-plane vertex.  The instance with the piece ring (1024 entries) walks the complement where a split
-leaves three vertices inside: for y, the x-piece whole and minus its one outside
-tetrahedron (two pieces instead of three); for x, when the tile holds the bbox's last
-row, minus the one outside tetrahedron (its D column then gets the last row's added).
+on-plane vertex.  Where the y split leaves three vertices inside, the kernel walks the x-piece whole and
+minus its one outside tetrahedron (two pieces instead of three); the instance with the
+piece ring (1024 entries) does the same for x when the tile holds the bbox's last row
+(minus the one outside tetrahedron; its D column then gets the last row's added).
 This module is measurement code: it shares no code with the kernels
 or with the oracle.
 """
@@ -131,8 +131,8 @@ def _split(V: np.ndarray, d: np.ndarray):
     return np.concatenate(out), np.concatenate(parent)
 
 
-# buffer sizes of the instances that walk their pieces through the ring, where the
-# splits that leave three vertices inside take the complement
+# buffer sizes of the instances that walk their pieces through the ring, where an x
+# split that leaves three vertices inside takes the complement
 RING_CAPS = (1024,)
 
 
@@ -231,25 +231,22 @@ def _count_batch(vr, ex, cap, counts):
     Y = (B[par1] + 1).astype(np.float64)
     cy = (B[par1] + 1) < ex[T[par1], 1]
     dy = np.where(cy[:, None], Y[:, None] - P1[:, :, 0], 1.0)
-    if ring:
-        # the y complement: three vertices inside y <= b+1 -> the x-piece whole and its
-        # one outside tetrahedron (cut points from the inside vertices toward it)
-        three = (dy >= 0).sum(axis=1) == 3
-        Pb, parb = _split(P1[~three][:, :, 1:], dy[~three])
-        Q = P1[three]
-        dq = dy[three]
-        perm = np.argsort(dq < 0, axis=1, kind="stable")     # inside first, then the outside one
-        Qp = np.take_along_axis(Q, perm[:, :, None], axis=1)
-        dp = np.take_along_axis(dq, perm, axis=1)
-        out = [Qp[:, 3]]
-        for q in range(3):
-            t = dp[:, q] / (dp[:, q] - dp[:, 3])
-            out.append(Qp[:, q] + t[:, None] * (Qp[:, 3] - Qp[:, q]))
-        idx3 = np.flatnonzero(three)
-        P2 = np.concatenate([Pb, Q[:, :, 1:], np.stack(out, axis=1)[:, :, 1:]])
-        par2 = np.concatenate([np.flatnonzero(~three)[parb], idx3, idx3])
-    else:
-        P2, par2 = _split(P1[:, :, 1:], dy)                  # carry z
+    # the y complement: three vertices inside y <= b+1 -> the x-piece whole and its
+    # one outside tetrahedron (cut points from the inside vertices toward it)
+    three = (dy >= 0).sum(axis=1) == 3
+    Pb, parb = _split(P1[~three][:, :, 1:], dy[~three])
+    Q = P1[three]
+    dq = dy[three]
+    perm = np.argsort(dq < 0, axis=1, kind="stable")     # inside first, then the outside one
+    Qp = np.take_along_axis(Q, perm[:, :, None], axis=1)
+    dp = np.take_along_axis(dq, perm, axis=1)
+    out = [Qp[:, 3]]
+    for q in range(3):
+        t = dp[:, q] / (dp[:, q] - dp[:, 3])
+        out.append(Qp[:, q] + t[:, None] * (Qp[:, 3] - Qp[:, q]))
+    idx3 = np.flatnonzero(three)
+    P2 = np.concatenate([Pb, Q[:, :, 1:], np.stack(out, axis=1)[:, :, 1:]])
+    par2 = np.concatenate([np.flatnonzero(~three)[parb], idx3, idx3])
     counts["piece"] += int(len(P2))
     col = par1[par2]
     z = P2[:, :, 0]

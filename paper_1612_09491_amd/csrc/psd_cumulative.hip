@@ -307,7 +307,9 @@ __device__ __forceinline__ void spread_z(const R z[4], R frac, const Tile& t, R*
     }
 }
 
-// D column (a,b) of one tile: T cut by x <= a+1 and y <= b+1.
+// D column (a,b) of one tile: T cut by x <= a+1 and y <= b+1 (where the y
+// split leaves three vertices inside, the x-piece whole minus its one outside
+// tetrahedron: two z walks instead of three).
 template <bool WORK>
 __device__ __forceinline__ void column(const CTet& S, int a, int b, const Tile& t, double* Dcol,
                                        WorkCount& wc)
@@ -385,10 +387,18 @@ __device__ __forceinline__ void column(const CTet& S, int a, int b, const Tile& 
         const double c3 = zb + s2.t3 * (zd - zb);
         const double u0 = za, u1 = (b3 || b4) ? zb : c0, u2 = (b3 || b4) ? zc : c1;
         const double w0 = b2 ? zb : c0, w1 = b2 ? c2 : c1, w2 = b4 ? zd : (b2 ? c3 : c2);
-        const int n2 = (b2 || b3) ? 3 : 1;
+        // three inside: the x-piece whole, then minus its one outside
+        // tetrahedron (zd, c0, c1, c2), whose edges from zd keep 1 - t
+        if (b3) {
+            s2.f0 = 1.0;
+            s2.f1 = -((1.0 - s2.t0) * (1.0 - s2.t1) * (1.0 - s2.t2));
+        }
+        const int n2 = b2 ? 3 : (b3 ? 2 : 1);
         if constexpr (WORK) wc.piece += (unsigned long long)n2;
         for (int k = 0; k < n2; ++k) {
-            const double z[4] = {u0, k == 2 ? w0 : u1, k == 0 ? u2 : w1, w2};
+            const bool c1k = b3 && k == 1;
+            const double z[4] = {c1k ? zd : u0, (k == 2 || c1k) ? w0 : u1, k == 0 ? u2 : w1,
+                                 (b3 && k == 0) ? zd : w2};
             const double f2 = k == 0 ? s2.f0 : (k == 1 ? s2.f1 : s2.f2);
             spread_z<WORK, double>(z, f1 * f2, t, Dcol, wc);
         }
