@@ -457,8 +457,8 @@ __device__ __forceinline__ void drain_round(PieceRing<QCAP, R>& Q, int& head, in
 // inside part is a prism of three pieces while the outside part x > a+1 is
 // one tetrahedron, and the tile holds the bbox's last row, whose D columns
 // are all of T below y = b+1 (no x plane cuts there).  Such a column is
-// walked as minus the outside tetrahedron, and the last row's column is added
-// to it once the walk is done (cumulative_add_last).
+// walked as minus the outside tetrahedron; the 2-D differences add the last
+// row's column back where the complement starts or ends.
 __device__ __forceinline__ bool x_complement(const CTet& S, const Tile& t, int a)
 {
     const double X = (double)(a + 1);
@@ -615,21 +615,6 @@ __device__ __forceinline__ void column_queue(bool valid, const CTet& S, int a, i
             if (count >= kWave) drain_round<WORK, QCAP, double>(Q, head, count, tiles, Dbuf, wc);
         }
     }
-}
-
-// After the walk of a batch: every column that took the x complement gets
-// the D column of its tile's last row (same b) added, level by level, which
-// makes it T's D column below y = b+1 minus the outside part's.
-__device__ __forceinline__ void cumulative_add_last(const CTet& S, const Tile& t, int r, double* Dbuf)
-{
-    const int wb = t.tb + t.hb;
-    const int qa = fdivi(r, t.inv_wb);
-    const int a = t.a0 - t.ha + qa;
-    if (!x_complement(S, t, a)) return;
-    const int qlast = t.ta + t.ha - 1;  // the last row of the tile (no x cut there)
-    double* Dcol = Dbuf + t.doff + r * t.tl;
-    const double* Dl = Dbuf + t.doff + (r + (qlast - qa) * wb) * t.tl;
-    for (int l = 0; l < t.tl; ++l) Dcol[l] += Dl[l];
 }
 
 // ---------------------------------------------------------------------------
@@ -1068,6 +1053,8 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
     static_assert(!SLAB || (QCAP > 0 && GROUP < 16), "the slab form queues its leaves");
     using DT = typename std::conditional<SLAB, float, double>::type;
     constexpr int SLAB_ROWS = SLAB ? 16 : 1;
+    // the ring's walk takes the x complement (column_queue)
+    constexpr bool XCMP = QCAP > 0 && !SLAB;
     __shared__ CTet slots[GROUP];
     __shared__ __attribute__((aligned(16))) DT Dbuf[CAP];
     __shared__ Tile tiles[TILES];
@@ -1398,17 +1385,6 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
                     while (count > 0)
                         drain_round<WORK, QCAP, DT>(ring, head, count, tiles, Dbuf, wc, SLAB);
                     __syncthreads();
-                    if constexpr (!SLAB) {
-                        for (int64_t base = 0; base < total; base += kWave) {
-                            const int64_t idx = base + lane;
-                            if (idx < total) {
-                                int lo = 0, r = 0;
-                                locate(idx, lo, r);
-                                cumulative_add_last(slots[t_slot[lo]], tiles[lo], r, Dbuf);
-                            }
-                        }
-                        __syncthreads();
-                    }
                 }
                 for (int64_t base = 0; base < total; base += kWave) {
                     const int64_t idx = base + lane;
@@ -1448,6 +1424,27 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
                             const DT* D00 = (has_a && has_b) ? D11 - (wb + 1) * t.tl : D11;
                             const double ma = has_a ? 1.0 : 0.0, mb = has_b ? 1.0 : 0.0;
                             const double mab = ma * mb;
+                            // Rows that took the x complement hold D minus the last
+                            // row's column: across a row where that starts (ce = 1)
+                            // or ends (ce = -1, the last row) the difference also
+                            // carries the last row's own y difference E(b) - E(b-1).
+                            double ce = 0.0;
+                            const DT* E1 = D11;
+                            const DT* E0 = D11;
+                            if constexpr (XCMP) {
+                                const int a = t.a0 + i;
+                                const bool c1 = x_complement(S, t, a);
+                                const bool c0 = a > 0 && x_complement(S, t, a - 1);
+                                ce = (c1 ? 1.0 : 0.0) - (c0 ? 1.0 : 0.0);
+                                E1 = Dbuf + t.doff + ((t.ta + t.ha - 1) * wb + cb) * t.tl;
+                                E0 = has_b ? E1 - t.tl : E1;
+                            }
+                            auto volume = [&](int l) {
+                                double V = fma(-ma, (double)D01[l], (double)D11[l]) -
+                                           fma(-mab, (double)D00[l], mb * (double)D10[l]);
+                                if constexpr (XCMP) V = fma(ce, fma(-mb, (double)E0[l], (double)E1[l]), V);
+                                return V;
+                            };
                             // grid cell of level 0, and the grid axis the levels walk
                             const int o0 = t.a0 + i, o1 = t.b0 + j, o2 = t.l0;
                             const int k0 = walk_axis(S, 0), k1 = walk_axis(S, 1), k2 = walk_axis(S, 2);
@@ -1483,8 +1480,7 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
                                                              : (k2 == 1 ? (int64_t)P.nc[2] : 1);
                                 OutT* po = out + ((int64_t)gx * P.nc[1] + gy) * P.nc[2] + gz;
                                 auto cell = [&](int l) {
-                                    const double V = fma(-ma, (double)D01[l], (double)D11[l]) -
-                                                     fma(-mab, (double)D00[l], mb * (double)D10[l]);
+                                    const double V = volume(l);
                                     if (V > 4e-15) {
                                         ++n_nz;
                                         const double mass = P.m * V;
@@ -1515,8 +1511,7 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
                                 int qw = k2 == 0 ? cx : (k2 == 1 ? cy : cz);
                                 int leaf = global_view(P.leaf_map)[node];
                                 for (int l = 0; l < t.tl; ++l) {
-                                    const double V = fma(-ma, (double)D01[l], (double)D11[l]) -
-                                                     fma(-mab, (double)D00[l], mb * (double)D10[l]);
+                                    const double V = volume(l);
                                     if (V > 4e-15 && leaf >= 0) {
                                         ++n_nz;
                                         const double mass = P.m * V;
@@ -1542,8 +1537,7 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
                                 // octree level (large-tet instances, which have no
                                 // registers to spare): each non-zero cell mapped alone
                                 for (int l = 0; l < t.tl; ++l) {
-                                    const double V = fma(-ma, (double)D01[l], (double)D11[l]) -
-                                                     fma(-mab, (double)D00[l], mb * (double)D10[l]);
+                                    const double V = volume(l);
                                     if (V > 4e-15) {
                                         const int w = wrap_add(gw, l, nw);
                                         const int64_t gi = out_index(P, k2 == 0 ? w : gx,
