@@ -169,10 +169,18 @@ def count_events(pos: np.ndarray, nc, cubes: np.ndarray, cap: int = 1024,
     w1 = np.where(w2 == 2, 1, 2)
     axes = np.stack([w0, w1, w2], axis=1)
     vr = np.take_along_axis(V - lo[:, None, :], axes[:, None, :], axis=2)
+    ex = np.take_along_axis(ext, axes, axis=1)
+    # of the two shorter axes the first split goes along the one with fewer three-piece
+    # columns: (floor of the 3rd smallest coordinate - floor of the 2nd) x the other extent
+    srt = np.sort(vr[:, :, :2], axis=1)
+    rows = np.floor(srt[:, 2]) - np.floor(srt[:, 1])
+    swap = rows[:, 1] * ex[:, 0] < rows[:, 0] * ex[:, 1]
+    order = np.where(swap[:, None], [1, 0, 2], [0, 1, 2])
+    vr = np.take_along_axis(vr, order[:, None, :], axis=2)
     # the kernel keeps each tetrahedron's vertices in increasing walk-frame x
     # (ties by vertex index), which fixes the triangulation of its pieces
     vr = np.take_along_axis(vr, np.argsort(vr[:, :, 0], axis=1, kind="stable")[:, :, None], axis=1)
-    ex = np.take_along_axis(ext, axes, axis=1)
+    ex = np.take_along_axis(ex, order, axis=1)
     for s in range(0, len(vr), batch_tets):
         _count_batch(vr[s:s + batch_tets], ex[s:s + batch_tets], cap, counts)
     return counts

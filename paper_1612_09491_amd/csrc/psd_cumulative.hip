@@ -965,7 +965,33 @@ __device__ __forceinline__ int setup_tet(const BoxDesc& P, int64_t tid, CTet& S,
     if (P.skip_small && ncell >= 2 && e[0] <= 2 && e[1] <= 2 && e[2] <= 2) return 0;
     // walk frame: the longest axis last (ties keep the later grid axis)
     const int w2 = (e[0] > e[1] && e[0] > e[2]) ? 0 : (e[1] > e[2] ? 1 : 2);
-    const int w0 = w2 == 0 ? 1 : 0, w1 = w2 == 2 ? 1 : 2;
+    int w0 = w2 == 0 ? 1 : 0, w1 = w2 == 2 ? 1 : 2;
+    {
+        // Of the two others, the first split goes along the one with fewer
+        // three-piece columns: rows whose plane has two vertices on each side
+        // (floor of the 3rd smallest coordinate minus floor of the 2nd, in
+        // bbox-local units) times the row's length, the other axis' extent.
+        double rows[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int c = k == 0 ? w0 : w1;
+            const double lo = c == 0 ? lof[0] : (c == 1 ? lof[1] : lof[2]);
+            double x[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) x[q] = (c == 0 ? T.v[q][0] : (c == 1 ? T.v[q][1] : T.v[q][2])) - lo;
+            const double a = fmin(x[0], x[1]), b = fmax(x[0], x[1]);
+            const double cc = fmin(x[2], x[3]), d = fmax(x[2], x[3]);
+            const double m1 = fmin(fmax(a, cc), fmin(b, d)), m2 = fmax(fmax(a, cc), fmin(b, d));
+            rows[k] = floor(m2) - floor(m1);
+        }
+        const int e0 = w0 == 0 ? e[0] : (w0 == 1 ? e[1] : e[2]);
+        const int e1 = w1 == 0 ? e[0] : (w1 == 1 ? e[1] : e[2]);
+        if (rows[1] * (double)e0 < rows[0] * (double)e1) {
+            const int t = w0;
+            w0 = w1;
+            w1 = t;
+        }
+    }
     S.axes = w0 | (w1 << 2) | (w2 << 4);
     const int wa[3] = {w0, w1, w2};
     double w[4][3];
