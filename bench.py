@@ -184,7 +184,8 @@ def atomic_peaks(torch) -> dict:
     blocks = 256 * 16
     out = {}
     for name, pat in (("global_atomic_add_f32_coalesced", 0), ("global_atomic_add_f32_random", 1),
-                      ("global_atomic_add_f32_column_walks", 2)):
+                      ("global_atomic_add_f32_column_walks", 2),
+                      ("global_atomic_add_f32_tile_rows", 3)):
         def run(pat=pat):
             n = L.peaks_global_atomic_f32(buf.data_ptr(), words, blocks, 64, pat, sh)
             if n < 0:
@@ -282,9 +283,10 @@ def own_work(pos: np.ndarray, nc, n_cubes: int, cap: int, nz_per_tet: float,
 
 
 # template arguments after the buffer size of each deposit-kernel instance:
-# tets set up at once, tiles per batch
-GROUP_OF_CAP = {512: "16, 16, false, 0", 960: "32, 16, false, 0", 1024: "8, 8, false, 128",
-                1408: "8, 8, false, 0", 2048: "32, 32, false, 0"}
+# tets set up at once, tiles per batch, work counters, ring size, slab form
+GROUP_OF_CAP = {512: "16, 16, false, 0, false", 960: "32, 16, false, 0, false",
+                1024: "8, 8, false, 128, false", 1408: "8, 8, false, 0, false",
+                2048: "32, 32, false, 0, false"}
 
 SURROGATE_WEIGHTS = os.path.join(ROOT, "paper_1612_09491_amd", "surrogate_zel256_g64.npy")
 
@@ -427,11 +429,13 @@ def roofline_line(kernel: str, kernel_ms: float, ntet: int, own: dict | None,
             "equivalent_frac": paper_ops * ntet / t / PEAK_VALU_OPS,
             "note": "the paper's per-cell splitting priced with its frozen unit costs: the "
                     "work that method would do at this speed, not a fraction of a roofline"}
-    if n_atomic is not None and peaks and "global_atomic_add_f32_column_walks" in peaks:
-        # the deposit's scatter: each lane walks its column's levels along one axis
-        pa = peaks["global_atomic_add_f32_column_walks"]
+    if n_atomic is not None and peaks and "global_atomic_add_f32_tile_rows" in peaks:
+        # the deposit's scatter: the lanes hold a tile's columns row by row (neighbouring
+        # cells along one grid axis), each walking its column's levels along another
+        pa = peaks["global_atomic_add_f32_tile_rows"]
         terms["atomic_s"] = n_atomic / pa
-        line["atomic"] = {"n_atomic": n_atomic, "peak_column_walks": pa,
+        line["atomic"] = {"n_atomic": n_atomic, "peak_tile_rows": pa,
+                          "peak_column_walks": peaks.get("global_atomic_add_f32_column_walks"),
                           "peak_random": peaks.get("global_atomic_add_f32_random"),
                           "peak_coalesced": peaks.get("global_atomic_add_f32_coalesced"),
                           "achieved": n_atomic / t, "frac": n_atomic / t / pa,
@@ -524,7 +528,7 @@ def bench_octree(args, torch, psd) -> dict:
                                           f"onto the finest level's {nc_f}^3 cells, "
                                           f"{o['seconds']:.1f} s"}
         own = own_work(pos, nc_f, args.model_cubes, 960, o["nz_per_tet"])
-        line["roofline"] = roofline_line("queue_kernel<float, 960, 32, 16, false, 0>", kernel_ms, ntet, own,
+        line["roofline"] = roofline_line("queue_kernel<float, 960, 32, 16, false, 0, false>", kernel_ms, ntet, own,
                                          o["paper_ops_per_tet"], o["nz_per_tet"] * ntet,
                                          12.0 * pos.shape[0] ** 3 + out.numel() * 4.0,
                                          None, None, None)
@@ -792,7 +796,7 @@ def main() -> int:
         nz_per_tet = cnt["n_nonzero"] / max(cnt["n_tet"], 1)
         own = own_work(pos, nc, args.model_cubes, 1024, nz_per_tet)
         own["gpu_events_per_tet"] = {k: v / ntet for k, v in gwork.items()}
-        roofline = roofline_line("queue_kernel<float, 1024, 8, 8, false, 128>", kernel_ms, ntet, own,
+        roofline = roofline_line("queue_kernel<float, 1024, 8, 8, false, 128, false>", kernel_ms, ntet, own,
                                  paper_ops_per_tet(pcnt), nz_per_tet * ntet,
                                  12.0 * p["np"] ** 3 + 4.0 * nc ** 3, peaks, clk.summary(),
                                  load_traffic("queue_kernel", WORKLOAD))

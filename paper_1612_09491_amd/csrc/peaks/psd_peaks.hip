@@ -13,9 +13,14 @@
 //     one axis of a 512^3 grid from a hashed start, the axis (stride 1, 512
 //     or 512^2 words) the same across a wavefront and changing from one
 //     wavefront to the next -- the deposit's phase 2, where each lane walks
-//     the levels of its own column along the tetrahedron's walk axis.  n is a
-//     power of two and addresses are masked to n - 1, so every access is in
-//     bounds.
+//     the levels of its own column along the tetrahedron's walk axis;
+//     pattern 3: the lanes in groups of 8 (a tile row of 8 neighbouring
+//     columns, one cell apart along one axis of the 512^3 grid) from a hashed
+//     start per group, each lane walking runs of 8 cells along another axis,
+//     the pair of axes the same across a wavefront and one of the six from
+//     one wavefront to the next -- phase 2 as the deposit lays its columns
+//     out, row by row over the lanes.  n is a power of two and addresses are
+//     masked to n - 1, so every access is in bounds.
 //   peaks_lds_atomic: LDS atomic adds without return (ds_add_f32 or
 //     ds_add_f64, the deposit's level increments) to lane-consecutive words
 //     of a 2048-word array per workgroup, bank-conflict free.
@@ -48,11 +53,19 @@ __global__ __launch_bounds__(kBlock) void global_atomic_kernel(float* __restrict
             a = ((uint32_t)i * nthreads + tid) & mask;
         } else if (pattern == 1) {
             a = mix32(tid * 0x9e3779b9u + (uint32_t)i * 0x85ebca6bu) & mask;
-        } else {
+        } else if (pattern == 2) {
             const uint32_t wave = tid >> 6;
             const uint32_t stride = (wave % 3u) == 0u ? 1u : ((wave % 3u) == 1u ? 512u : 512u * 512u);
             const uint32_t start = mix32(tid * 0x9e3779b9u + (uint32_t)(i >> 3) * 0x85ebca6bu);
             a = (start + (uint32_t)(i & 7) * stride) & mask;
+        } else {
+            const uint32_t wave = tid >> 6, pair = wave % 6u;
+            const uint32_t s[3] = {1u, 512u, 512u * 512u};
+            const uint32_t across = s[pair / 2u];                            // along the row
+            const uint32_t walk = s[(pair / 2u + 1u + (pair & 1u)) % 3u];    // another axis
+            const uint32_t group = tid >> 3;
+            const uint32_t start = mix32(group * 0x9e3779b9u + (uint32_t)(i >> 3) * 0x85ebca6bu);
+            a = (start + (tid & 7u) * across + (uint32_t)(i & 7) * walk) & mask;
         }
         __hip_atomic_fetch_add(buf + a, 1.0f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -88,7 +101,7 @@ int64_t peaks_global_atomic_f32(float* buf, int64_t n, int blocks, int iters, in
                                 void* stream)
 {
     if (!buf || n < 1 || n > (1ll << 31) || (n & (n - 1)) != 0 || blocks < 1 || iters < 1 ||
-        pattern < 0 || pattern > 2)
+        pattern < 0 || pattern > 3)
         return -1;
     hipLaunchKernelGGL(global_atomic_kernel, dim3(blocks), dim3(kBlock), 0,
                        reinterpret_cast<hipStream_t>(stream), buf, (uint32_t)(n - 1), iters, pattern);

@@ -36,7 +36,7 @@ def test_own_work_model_is_the_frozen_one():
 
 def test_roofline_terms_and_fraction():
     own = {"ops_per_tet": 1000.0}
-    peaks = {"global_atomic_add_f32_column_walks": 1e10, "global_atomic_add_f32_random": 5e9,
+    peaks = {"global_atomic_add_f32_tile_rows": 1e10, "global_atomic_add_f32_random": 5e9,
              "global_atomic_add_f32_coalesced": 4e10}
     # 1e6 tets in 10 ms: 1e9 ops -> 1e11 op/s against 3.93e13
     r = bench.roofline_line("k", 10.0, 10 ** 6, own, 2000.0, 5e7, 8e9, peaks, None, None)
