@@ -52,10 +52,13 @@ __device__ __forceinline__ int walk_axis(const CTet& S, int k) { return (S.axes 
 // A tile of one tetrahedron's cells: x in [a0, a0+ta), y in [b0, b0+tb),
 // z in [l0, l0+tl).  Its D buffer covers columns a in [a0-ha, a0+ta),
 // b in [b0-hb, b0+tb) (ha, hb = 1 when a lower neighbour column exists).
+// Extents and the D offset are below the buffer size (<= 4096 entries), so
+// they take 16 bits: a 28-byte record.
 struct Tile {
-    int a0, ta, b0, tb, l0, tl;
-    int ha, hb;
-    int doff;        // offset in the D buffer
+    int a0, b0, l0;
+    int16_t ta, tb, tl;
+    int16_t doff;    // offset in the D buffer
+    uint8_t ha, hb;
     float inv_wb;    // 1 / (tb + hb), the hardware reciprocal (fdivi's bound holds for it)
 };
 
@@ -427,7 +430,7 @@ template <int QCAP, typename R>
 struct PieceRing {
     R z[4][QCAP];
     R frac[QCAP];
-    int where[QCAP];  // D offset << 8 | tile
+    uint16_t where[QCAP];  // D offset << 4 | tile
 };
 
 // The z walks of the next min(count, 64) queued pieces, one per lane.
@@ -444,9 +447,9 @@ __device__ __forceinline__ void drain_round(PieceRing<QCAP, R>& Q, int& head, in
         const int q = (head + lane) & (QCAP - 1);
         const R z[4] = {Q.z[0][q], Q.z[1][q], Q.z[2][q], Q.z[3][q]};
         const int w = Q.where[q];
-        Tile t = tiles[w & 0xFF];
+        Tile t = tiles[w & 15];
         if (local_z) t.l0 = 0;  // heights relative to the tile's first level
-        spread_z<WORK, R>(z, Q.frac[q], t, Dbuf + (w >> 8), wc);
+        spread_z<WORK, R>(z, Q.frac[q], t, Dbuf + (w >> 4), wc);
     }
     head = (head + ntake) & (QCAP - 1);
     count -= ntake;
@@ -609,7 +612,7 @@ __device__ __forceinline__ void column_queue(bool valid, const CTet& S, int a, i
                 Q.z[2][q] = k == 0 ? u2 : w1;
                 Q.z[3][q] = (ycmp && k == 0) ? e : w2;
                 Q.frac[q] = f1 * (k == 0 ? s2.f0 : (k == 1 ? s2.f1 : s2.f2));
-                Q.where[q] = (doff << 8) | tile_idx;
+                Q.where[q] = (uint16_t)((doff << 4) | tile_idx);
             }
             count += __popcll(bal);
             if (count >= kWave) drain_round<WORK, QCAP, double>(Q, head, count, tiles, Dbuf, wc);
@@ -851,7 +854,7 @@ __device__ __forceinline__ void column_slab(bool valid, const CTet& S, int b, co
                     Q.z[2][q] = k == 0 ? u2 : w1;
                     Q.z[3][q] = w2;
                     Q.frac[q] = f1 * (k == 0 ? s2.f0 : (k == 1 ? s2.f1 : s2.f2));
-                    Q.where[q] = (doff << 8) | tile_idx;
+                    Q.where[q] = (uint16_t)((doff << 4) | tile_idx);
                 }
                 count += __popcll(bal);
                 if (count >= kWave) drain_round<WORK, QCAP, float>(Q, head, count, tiles, Dbuf, wc, true);
@@ -1074,8 +1077,10 @@ template <typename OutT, int CAP, int GROUP, int TILES, bool WORK, int QCAP, boo
 __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) void queue_kernel(QueueArgs Q)
 {
     static_assert(kWave % GROUP == 0 && GROUP <= kWave && TILES <= GROUP, "chunk of whole groups");
-    static_assert(QCAP == 0 || (QCAP >= 2 * kWave && (QCAP & (QCAP - 1)) == 0 && TILES <= 256 &&
-                                CAP < (1 << 23)), "piece ring: a power of two of at least 128");
+    static_assert(QCAP == 0 || (QCAP >= 2 * kWave && (QCAP & (QCAP - 1)) == 0 && TILES <= 16 &&
+                                CAP <= 4096), "piece ring: a power of two of at least 128; its "
+                                              "records hold D offset and tile in 16 bits");
+    static_assert(CAP <= 32767 && TILES <= 256 && GROUP <= 256, "16-bit tile fields, 8-bit slots");
     static_assert(!SLAB || (QCAP > 0 && GROUP < 16), "the slab form queues its leaves");
     using DT = typename std::conditional<SLAB, float, double>::type;
     constexpr int SLAB_ROWS = SLAB ? 16 : 1;
@@ -1084,8 +1089,8 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
     __shared__ CTet slots[GROUP];
     __shared__ __attribute__((aligned(16))) DT Dbuf[CAP];
     __shared__ Tile tiles[TILES];
-    __shared__ int t_slot[TILES];
-    __shared__ int64_t s_incl[TILES];
+    __shared__ uint8_t t_slot[TILES];
+    __shared__ uint16_t s_incl[TILES];  // columns of the batch's tiles, inclusive prefix (<= CAP)
     __shared__ int64_t s_item;
     __shared__ PieceRing<(QCAP > 0 ? QCAP : 1), DT> ring;
     __shared__ SlabCache<SLAB_ROWS> slab;
@@ -1339,16 +1344,17 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
             // are in this window or an earlier one, and right after a barrier
             // phase 2 can walk the cells of the window's own columns.
             {
-                const int64_t c = lane < nt ? tile_cols(tiles[lane]) : 0;
-                int64_t incl = c;
+                // columns of a tile are at most its D entries, so the sums stay below CAP
+                const int c = lane < nt ? tile_cols(tiles[lane]) : 0;
+                int incl = c;
 #pragma unroll
                 for (int off = 1; off < kWave; off <<= 1) {
-                    const int64_t y = __shfl_up(incl, off, kWave);
+                    const int y = __shfl_up(incl, off, kWave);
                     if (lane >= off) incl += y;
                 }
-                if (lane < TILES) s_incl[lane] = incl;  // nt <= TILES
+                if (lane < TILES) s_incl[lane] = (uint16_t)incl;  // nt <= TILES
                 __syncthreads();
-                const int64_t total = __shfl(incl, kWave - 1, kWave);
+                const int total = __shfl(incl, kWave - 1, kWave);
                 // the tile of pair idx and its column's rank r within the tile
                 auto locate = [&](int64_t idx, int& lo, int& r) {
                     lo = 0;
