@@ -1524,7 +1524,12 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
                                     po += step;
                                 };
                                 const int lw = min(t.tl, nw - gw);
-                                for (int l = 0; l < lw; ++l) cell(l);
+                                int l = 0;
+                                for (; l + 1 < lw; l += 2) {  // pairs: one ds_read2 per D column
+                                    cell(l);
+                                    cell(l + 1);
+                                }
+                                if (l < lw) cell(l);
                                 po -= step * nw;
                                 for (int l = lw; l < t.tl; ++l) cell(l);
                             } else if constexpr (CAP <= 960) {
