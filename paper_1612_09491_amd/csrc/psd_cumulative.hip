@@ -62,7 +62,7 @@ struct Tile {
     float inv_wb;    // 1 / (tb + hb), the hardware reciprocal (fdivi's bound holds for it)
 };
 
-// q = n / d for 0 <= n < 2^20 via a float reciprocal of relative error up to
+// q = n / d for 0 <= n < 2^21 via a float reciprocal of relative error up to
 // 2^-23 (the hardware's): (n + 1/2) * inv_d is off from (n + 1/2) / d by less
 // than (n + 1/2) * 1.8e-7 / d < 1/(2d), so it stays inside (q, q + 1).
 __device__ __forceinline__ int fdivi(int n, float inv_d)
@@ -109,7 +109,9 @@ __device__ __forceinline__ int64_t out_index(const BoxDesc& P, int x, int y, int
 {
     if (!P.leaf_map) return ((int64_t)x * P.nc[1] + y) * P.nc[2] + z;
     const int B = P.leaf_block, side = P.leaf_side;
-    const int nx = x / B, ny = y / B, nz = z / B;
+    // cells below 2^20 (the largest grid): node quotients by fdivi
+    const float invB = __builtin_amdgcn_rcpf((float)B);
+    const int nx = fdivi(x, invB), ny = fdivi(y, invB), nz = fdivi(z, invB);
     const int leaf = global_view(P.leaf_map)[(nx * side + ny) * side + nz];
     if (leaf < 0) return -1;
     return (int64_t)leaf * B * B * B + ((x - nx * B) * B + (y - ny * B)) * B + (z - nz * B);
@@ -1597,18 +1599,36 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
         __syncthreads();
         if constexpr (AGG) {
             if (tiled) {
-                // the group tile to the grid: one atomic per non-zero cell
+                // the group tile to the grid: one atomic per non-zero cell.
+                // Cell i of the tile is (i / (E1 E2), i / E2 mod E1, i mod E2)
+                // and its grid cell (base + that) mod nc, base the tile's
+                // origin wrapped once; every quotient has a numerator below
+                // 2^21 (i < 192, base + offset < nc + 192 with nc <= 2^20), so it
+                // comes from a float reciprocal (fdivi), not an integer division.
                 const int ncells = gE[0] * gE[1] * gE[2];
+                const int e12 = gE[1] * gE[2];
+                const float inv12 = __builtin_amdgcn_rcpf((float)e12);
+                const float inv2 = __builtin_amdgcn_rcpf((float)gE[2]);
+                int base[3];
+                float invn[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int nca = P.nc[c];
+                    const int x = (gref[c] + gmn[c]) % nca;
+                    base[c] = x < 0 ? x + nca : x;
+                    invn[c] = __builtin_amdgcn_rcpf((float)nca);
+                }
                 for (int i = lane; i < ncells; i += kWave) {
                     const OutT v = acc[i];
                     if (v == OutT(0)) continue;
-                    const int li[3] = {i / (gE[1] * gE[2]), (i / gE[2]) % gE[1], i % gE[2]};
+                    const int q0 = fdivi(i, inv12), r0 = i - q0 * e12;
+                    const int q1 = fdivi(r0, inv2);
+                    const int li[3] = {q0, q1, r0 - q1 * gE[2]};
                     int g3[3];
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        const int nca = P.nc[c];
-                        int x = (gref[c] + gmn[c] + li[c]) % nca;
-                        g3[c] = x < 0 ? x + nca : x;
+                        const int x = base[c] + li[c];
+                        g3[c] = x - fdivi(x, invn[c]) * P.nc[c];
                     }
                     const int64_t idx = out_index(P, g3[0], g3[1], g3[2]);
                     if (idx >= 0) global_add(out + idx, v);

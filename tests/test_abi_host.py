@@ -111,21 +111,25 @@ def test_launch_shape_validation(psd):
 
 
 def test_float_reciprocal_quotient_is_exact():
-    """The deposit kernel divides column indices n < 2^20 by small integers d
-    (a tile's width in columns) as trunc((n + 1/2) * (1/d))
-    in FP32, with 1/d rounded to float: the rounding error stays below the
-    1/(2d) that separates (n + 1/2)/d from an integer, so the quotient is
-    exact.  Checked here with IEEE FP32 arithmetic for every n."""
+    """The deposit kernel divides indices n < 2^21 (columns of a tile, cells
+    of a group tile, grid cells plus a tile offset) by integers d up to 2^20
+    (a tile's width, a leaf side, a grid side) as trunc((n + 1/2) * r) in
+    FP32, r the hardware reciprocal of d (within one ulp of 1/d): the error
+    stays below the 1/(2d) that separates (n + 1/2)/d from an integer, so the
+    quotient is exact.  Checked here with IEEE FP32 arithmetic for every n and
+    for 1/d rounded to float and one ulp either side."""
     import numpy as np
-    n = np.arange(1 << 20, dtype=np.int64)
+    n = np.arange(1 << 21, dtype=np.int64)
     nf = n.astype(np.float32) + np.float32(0.5)
     rng = np.random.default_rng(7)
-    ds = sorted(set(range(1, 65)) | {1 << k for k in range(13)} | {4095, 4093, 3001, 2047}
-                | set(int(d) for d in rng.integers(65, 4097, 60)))
+    ds = sorted(set(range(1, 65)) | {1 << k for k in range(21)} | {4095, 4093, 3001, 2047}
+                | set(int(d) for d in rng.integers(65, 4097, 60))
+                | set(int(d) for d in rng.integers(4097, (1 << 20) + 1, 20)))
     for d in ds:
-        inv = np.float32(1.0 / d)
-        q = (nf * inv).astype(np.int64)
-        assert np.array_equal(q, n // d), d
+        r = np.float32(1.0 / d)
+        for inv in (r, np.nextafter(r, np.float32(0)), np.nextafter(r, np.float32(1))):
+            q = (nf * inv).astype(np.int64)
+            assert np.array_equal(q, n // d), (d, inv)
 
 
 def test_octree_leaf_side_limit(psd):
