@@ -928,9 +928,7 @@ __device__ __forceinline__ int setup_tet(const BoxDesc& P, int64_t tid, CTet& S,
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const double x = 0.25 * (T.v[0][c] + T.v[1][c] + T.v[2][c] + T.v[3][c]);
-            const double fl = floor(x);
-            const double n = (double)P.nc[c];
-            g[c] = (int)(fl - n * floor(fl / n));
+            g[c] = wrap_index(floor(x), P.nc[c]);
         }
         const int64_t idx = out_index(P, g[0], g[1], g[2]);
         if (idx >= 0) {
@@ -958,8 +956,7 @@ __device__ __forceinline__ int setup_tet(const BoxDesc& P, int64_t tid, CTet& S,
         e[c] = (int)(floor(mx) - lof[c]) + 1;
         // minimum-image offsets bound the extent by nc + 1 cells
         ok = ok && e[c] >= 1 && e[c] <= P.nc[c] + 1;
-        const double n = (double)P.nc[c];
-        S.lo[c] = (int)(lof[c] - n * floor(lof[c] / n));
+        S.lo[c] = wrap_index(lof[c], P.nc[c]);
     }
     // a bbox can exceed 2^31 cells on grids above ~1290 cells per axis: the
     // count only picks the tiled walk, which handles any size

@@ -47,6 +47,15 @@ __device__ __forceinline__ void global_add(T* p, T v)
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// A cell index of an unwrapped tetrahedron (an integer-valued double in
+// [-n, 2n): its vertices lie within half a box of corner 0, which is in
+// [0, n)) wrapped into [0, n) without a division.
+__device__ __forceinline__ int wrap_index(double x, int n)
+{
+    const int i = (int)x;
+    return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+
 // Quotient a / b for b > 0 with a few ulps of error (the FP64 reciprocal
 // estimate refined by one Newton step, which doubles its correct bits).
 __device__ __forceinline__ float fdiv_pos(float a, float b)
@@ -315,13 +324,22 @@ __device__ __forceinline__ void make_tet(const float* __restrict__ pos, int np0,
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        double n = (double)nc[a];
-        double c0w = c[0][a] - n * floor(c[0][a] / n);
+        const double n = (double)nc[a];
+        // 1/n to about an ulp (the hardware estimate and two Newton steps)
+        // instead of a division per quotient: the quotients only pick integer
+        // shifts, a floor that lands corner 0 outside [0, n) (c/n within an ulp
+        // of an integer) is corrected to the same value, and the minimum image
+        // can differ only for a displacement within an ulp of half the box
+        double r = __builtin_amdgcn_rcp(n);
+        r = fma(fma(-n, r, 1.0), r, r);
+        r = fma(fma(-n, r, 1.0), r, r);
+        double c0w = c[0][a] - n * floor(c[0][a] * r);
+        c0w = c0w >= n ? c0w - n : (c0w < 0.0 ? c0w + n : c0w);
         T.v[0][a] = c0w;
 #pragma unroll
         for (int m = 1; m < 4; ++m) {
             double d = c[m][a] - c[0][a];
-            d -= n * rint(d / n);
+            d -= n * rint(d * r);
             T.v[m][a] = c0w + d;
         }
     }

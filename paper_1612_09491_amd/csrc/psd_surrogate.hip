@@ -1000,10 +1000,7 @@ __global__ __launch_bounds__(64, 2) void surrogate_deposit_kernel(UniformArgs P,
             for (int k = 0; k < kIn; ++k) qx[slot * kIn + k] = x[k];
             qm[slot * 4] = m | (r << 8);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const double n = (double)P.nc[a];
-                qm[slot * 4 + 1 + a] = (int)(lo[a] - n * floor(lo[a] / n));
-            }
+            for (int a = 0; a < 3; ++a) qm[slot * 4 + 1 + a] = wrap_index(lo[a], P.nc[a]);
             ++n_sur;
         }
         qn += (int)__popcll(bal);

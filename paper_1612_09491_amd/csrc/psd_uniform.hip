@@ -220,9 +220,7 @@ __global__ __launch_bounds__(kWave) void deposit_uniform_kernel(UniformArgs P)
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     const double x = 0.25 * (T.v[0][a] + T.v[1][a] + T.v[2][a] + T.v[3][a]);
-                    const double fl = floor(x);
-                    const double n = (double)P.nc[a];
-                    g[a] = (int)(fl - n * floor(fl / n));
+                    g[a] = wrap_index(floor(x), P.nc[a]);
                 }
                 scatter(out, P, g[0], g[1], g[2], P.m, macc);
             } else {
@@ -239,8 +237,7 @@ __global__ __launch_bounds__(kWave) void deposit_uniform_kernel(UniformArgs P)
                     // minimum-image offsets bound the extent by nc + 1 cells
                     ext_ok = ext_ok && ext[a] >= 1 && ext[a] <= P.nc[a] + 1;
                     frac |= (mx > hi) ? (1 << a) : 0;
-                    const double n = (double)P.nc[a];
-                    S.lo[a] = (int)(lo - n * floor(lo / n));
+                    S.lo[a] = wrap_index(lo, P.nc[a]);
                     S.ext[a] = ext[a];
 #pragma unroll
                     for (int v = 0; v < 4; ++v) S.vr[v][a] = T.v[v][a] - lo;
