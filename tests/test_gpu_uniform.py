@@ -321,3 +321,29 @@ def test_work_counters_match_cost_model(psd, orc, cap):
     ref, _ = orc.deposit_uniform(pos, p["nc"])
     got = out.double().cpu().numpy()
     assert _rel_l1(got, ref) <= FP32_L1 and _rel_linf(got, ref) <= FP32_LINF
+
+
+@pytest.mark.parametrize("cap", [1024, 1408])
+def test_work_counters_match_cost_model_tiled(psd, orc, cap):
+    """The same on tetrahedra of thousands of bbox cells (4^3 particles -> 48^3 cells),
+    which are tiled with halo rows and columns: the replay's tile shapes, halos, vertex
+    order, frame choice and complement walks (x only in tiles that hold the bbox's last
+    row) give the kernel's counts, and the FP64 grid meets the FP64 bar."""
+    import costmodel
+    pos = zeldovich_positions(4, 1.4, seed=44)
+    dev = torch.device("cuda:0")
+    pt = torch.from_numpy(pos).to(dev)
+    st = torch.zeros(16, dtype=torch.int64, device=dev)
+    out = psd.deposit_uniform(pt, 48, flags=psd.PSD_WORK_COUNTERS | psd.PSD_PREC_FP64, stats=st,
+                              tuning=(cap, 0, 0))
+    torch.cuda.synchronize()
+    s = st.cpu().numpy()
+    cm = costmodel.count_events(pos, 48, np.arange(4 ** 3), cap=cap)
+    gpu = {"column": s[2], "xpiece": s[8], "piece": s[9], "level": s[10], "colcell": s[11]}
+    print({k: (int(v), cm[k]) for k, v in gpu.items()})
+    assert cm["colcell"] > 4 * cap  # tiles of several tets' worth of cells
+    assert gpu["column"] == cm["column"] and gpu["colcell"] == cm["colcell"]
+    for k in ("xpiece", "piece", "level"):
+        assert abs(int(gpu[k]) - cm[k]) <= 1e-5 * cm[k] + 2, k
+    ref, _ = orc.deposit_uniform(pos, 48)
+    assert _rel_l1(out.cpu().numpy(), ref) <= FP64_L1
