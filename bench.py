@@ -450,8 +450,11 @@ def roofline_line(kernel: str, kernel_ms: float, ntet: int, own: dict | None,
         line["terms_s"] = terms
     if traffic and traffic.get("valu_insts_per_launch"):
         # machine view of the same launch: wave64 VALU instructions (rocprofv3
-        # SQ_INSTS_VALU of this kernel version) x 4 clocks over 1024 SIMDs
+        # SQ_INSTS_VALU of this kernel version) x 4 clocks over 1024 SIMDs, and the
+        # share of lanes active per VALU instruction (VALUUtilization)
         line["valu_issue_frac"] = 4.0 * traffic["valu_insts_per_launch"] / (SIMDS * CLOCK_HZ * t)
+        if traffic.get("valu_utilization_pct") is not None:
+            line["valu_lanes_active_frac"] = traffic["valu_utilization_pct"] / 100.0
     return line
 
 
