@@ -35,12 +35,11 @@ oracle's counting mode, reported beside it as an equivalent rate).  ``count_even
 replays the kernel's geometry on a sample of Lagrangian cubes in float64 numpy: the
 same unwrap, bbox, walk frame, tiling of large tetrahedra and piece triangulation, so
 its counts agree with the kernel's work counters except where rounding decides an
-on-plane vertex.  Where the y split leaves three vertices inside, the kernel walks the x-piece whole and
-minus its one outside tetrahedron (two pieces instead of three); the instance with the
-piece ring (1024 entries) does the same for x when the tile holds the bbox's last row
-(minus the one outside tetrahedron; its D column then gets the last row's added).
-This module is measurement code: it shares no code with the kernels
-or with the oracle.
+on-plane vertex.  Where a split leaves three vertices inside, the kernel walks the
+complement: for y, the x-piece whole and minus its one outside tetrahedron (two pieces
+instead of three); for x, when the tile holds the bbox's last row, minus the one outside
+tetrahedron (the 2-D differences then add the last row's column back).  This module is
+measurement code: it shares no code with the kernels or with the oracle.
 """
 
 from __future__ import annotations
@@ -131,11 +130,6 @@ def _split(V: np.ndarray, d: np.ndarray):
     return np.concatenate(out), np.concatenate(parent)
 
 
-# buffer sizes of the instances that walk their pieces through the ring, where an x
-# split that leaves three vertices inside takes the complement
-RING_CAPS = (1024,)
-
-
 def _tile_shape(ext, cap):
     tl = min(ext[2], cap // 4)
     tb = min(ext[1], cap // (2 * tl) - 1)
@@ -219,22 +213,18 @@ def _count_batch(vr, ex, cap, counts):
     X = (A + 1).astype(np.float64)
     cx = (A + 1) < ex[T, 0]
     dx = np.where(cx[:, None], X[:, None] - verts[:, :, 0], 1.0)
-    ring = cap in RING_CAPS
-    if ring:
-        # the x complement: three vertices inside x <= a+1 (vertices in increasing x)
-        # and the tile holding the bbox's last row -> the one outside tetrahedron
-        cmp = cx & (dx[:, 2] >= 0) & (dx[:, 3] < 0) & LAST
-        Pa, para = _split(verts[~cmp][:, :, 1:], dx[~cmp])
-        vc = verts[cmp]
-        d3 = vc[:, 3, 0] - X[cmp]
-        pts = [vc[:, 3]]
-        for q in range(3):
-            t = d3 / (d3 - (vc[:, q, 0] - X[cmp]))
-            pts.append(vc[:, 3] + t[:, None] * (vc[:, q] - vc[:, 3]))
-        P1 = np.concatenate([Pa, np.stack(pts, axis=1)[:, :, 1:]])
-        par1 = np.concatenate([np.flatnonzero(~cmp)[para], np.flatnonzero(cmp)])
-    else:
-        P1, par1 = _split(verts[:, :, 1:], dx)               # carry (y, z)
+    # the x complement: three vertices inside x <= a+1 (vertices in increasing x)
+    # and the tile holding the bbox's last row -> the one outside tetrahedron
+    cmp = cx & (dx[:, 2] >= 0) & (dx[:, 3] < 0) & LAST
+    Pa, para = _split(verts[~cmp][:, :, 1:], dx[~cmp])
+    vc = verts[cmp]
+    d3 = vc[:, 3, 0] - X[cmp]
+    pts = [vc[:, 3]]
+    for q in range(3):
+        t = d3 / (d3 - (vc[:, q, 0] - X[cmp]))
+        pts.append(vc[:, 3] + t[:, None] * (vc[:, q] - vc[:, 3]))
+    P1 = np.concatenate([Pa, np.stack(pts, axis=1)[:, :, 1:]])
+    par1 = np.concatenate([np.flatnonzero(~cmp)[para], np.flatnonzero(cmp)])
     counts["xpiece"] += int(len(P1))
     Y = (B[par1] + 1).astype(np.float64)
     cy = (B[par1] + 1) < ex[T[par1], 1]

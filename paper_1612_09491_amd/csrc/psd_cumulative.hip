@@ -312,9 +312,24 @@ __device__ __forceinline__ void spread_z(const R z[4], R frac, const Tile& t, R*
     }
 }
 
-// D column (a,b) of one tile: T cut by x <= a+1 and y <= b+1 (where the y
-// split leaves three vertices inside, the x-piece whole minus its one outside
-// tetrahedron: two z walks instead of three).
+// Whether column row a of tile t takes the complement of the x split: T has
+// three vertices with x <= a+1 (the vertices are in increasing x), so the
+// inside part is a prism of three pieces while the outside part x > a+1 is
+// one tetrahedron, and the tile holds the bbox's last row, whose D columns
+// are all of T below y = b+1 (no x plane cuts there).  Such a column is
+// walked as minus the outside tetrahedron; the 2-D differences add the last
+// row's column back where the complement starts or ends.
+__device__ __forceinline__ bool x_complement(const CTet& S, const Tile& t, int a)
+{
+    const double X = (double)(a + 1);
+    return a + 1 < S.ext[0] && X - S.vr[2][0] >= 0.0 && X - S.vr[3][0] < 0.0 &&
+           t.a0 + t.ta == S.ext[0];
+}
+
+// D column (a,b) of one tile: T cut by x <= a+1 and y <= b+1, the
+// complement walked where a split leaves three vertices inside (for y, the
+// x-piece whole minus its one outside tetrahedron: two z walks instead of
+// three; for x, see x_complement).
 template <bool WORK>
 __device__ __forceinline__ void column(const CTet& S, int a, int b, const Tile& t, double* Dcol,
                                        WorkCount& wc)
@@ -334,14 +349,30 @@ __device__ __forceinline__ void column(const CTet& S, int a, int b, const Tile& 
     double dx[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) dx[q] = cx ? X - v[q][0] : 1.0;
+    const int nin = (dx[0] >= 0.0 ? 1 : 0) + (dx[1] >= 0.0 ? 1 : 0) + (dx[2] >= 0.0 ? 1 : 0) +
+                    (dx[3] >= 0.0 ? 1 : 0);
+    const bool cmp = x_complement(S, t, a);
+    double d[4], P1[4][2];
+    d[0] = cmp ? -dx[3] : dx[0];
+    d[1] = cmp ? -dx[0] : dx[1];
+    d[2] = cmp ? -dx[1] : dx[2];
+    d[3] = cmp ? -dx[2] : dx[3];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        P1[0][c] = cmp ? v[3][c + 1] : v[0][c + 1];
+        P1[1][c] = cmp ? v[0][c + 1] : v[1][c + 1];
+        P1[2][c] = cmp ? v[1][c + 1] : v[2][c + 1];
+        P1[3][c] = cmp ? v[2][c + 1] : v[3][c + 1];
+    }
+    const double xsign = cmp ? -1.0 : 1.0;
     Split<double> s1;
-    split_prefix(dx, s1);
+    s1.nin = cmp ? 1 : nin;
+    s1.ia = 0;
+    s1.ib = 1;
+    s1.ic = 2;
+    s1.id = 3;
+    split_ordered(d[0], d[1], d[2], d[3], s1.nin, s1);
     if (s1.nin == 0) return;
-    double P1[4][2];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) P1[q][c] = v[q][c + 1];
     const bool a1 = s1.nin == 1, a2 = s1.nin == 2, a3 = s1.nin == 3, a4 = s1.nin == 4;
     double U0[2], U1[2], U2[2], W0[2], W1[2], W2[2];
 #pragma unroll
@@ -371,7 +402,7 @@ __device__ __forceinline__ void column(const CTet& S, int a, int b, const Tile& 
             cv[2][c] = j == 0 ? U2[c] : W1[c];
             cv[3][c] = W2[c];
         }
-        const double f1 = j == 0 ? s1.f0 : (j == 1 ? s1.f1 : s1.f2);
+        const double f1 = xsign * (j == 0 ? s1.f0 : (j == 1 ? s1.f1 : s1.f2));
         // level 2: y <= Y
         double dy[4];
 #pragma unroll
@@ -455,20 +486,6 @@ __device__ __forceinline__ void drain_round(PieceRing<QCAP, R>& Q, int& head, in
     }
     head = (head + ntake) & (QCAP - 1);
     count -= ntake;
-}
-
-// Whether column row a of tile t takes the complement of the x split: T has
-// three vertices with x <= a+1 (the vertices are in increasing x), so the
-// inside part is a prism of three pieces while the outside part x > a+1 is
-// one tetrahedron, and the tile holds the bbox's last row, whose D columns
-// are all of T below y = b+1 (no x plane cuts there).  Such a column is
-// walked as minus the outside tetrahedron; the 2-D differences add the last
-// row's column back where the complement starts or ends.
-__device__ __forceinline__ bool x_complement(const CTet& S, const Tile& t, int a)
-{
-    const double X = (double)(a + 1);
-    return a + 1 < S.ext[0] && X - S.vr[2][0] >= 0.0 && X - S.vr[3][0] < 0.0 &&
-           t.a0 + t.ta == S.ext[0];
 }
 
 // Column (a,b) of one tile (valid lanes only; every lane of the wavefront
@@ -1083,8 +1100,8 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
     static_assert(!SLAB || (QCAP > 0 && GROUP < 16), "the slab form queues its leaves");
     using DT = typename std::conditional<SLAB, float, double>::type;
     constexpr int SLAB_ROWS = SLAB ? 16 : 1;
-    // the ring's walk takes the x complement (column_queue)
-    constexpr bool XCMP = QCAP > 0 && !SLAB;
+    // the cumulative walk takes the x complement (column, column_queue)
+    constexpr bool XCMP = !SLAB;
     __shared__ CTet slots[GROUP];
     __shared__ __attribute__((aligned(16))) DT Dbuf[CAP];
     __shared__ Tile tiles[TILES];
@@ -1337,11 +1354,12 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
             __syncthreads();
             if (nt == 0) continue;
 
-            // (tile, column) pairs over lanes, 64 at a time.  Phase 1 fills
-            // the window's D columns; columns are numbered row by row, so the
-            // lower neighbours (a-1, b), (a, b-1), (a-1, b-1) of every column
-            // are in this window or an earlier one, and right after a barrier
-            // phase 2 can walk the cells of the window's own columns.
+            // (tile, column) pairs over lanes, 64 at a time, columns numbered
+            // row by row.  Phase 1 fills the D columns of every window of the
+            // batch (one column per lane, or through the piece ring); after a
+            // barrier phase 2 walks the cells of each window's columns, whose
+            // lower neighbours (a-1, b), (a, b-1), (a-1, b-1) and, for the x
+            // complement, the tile's last row are then final.
             {
                 // columns of a tile are at most its D entries, so the sums stay below CAP
                 const int c = lane < nt ? tile_cols(tiles[lane]) : 0;
@@ -1417,12 +1435,14 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
                         drain_round<WORK, QCAP, DT>(ring, head, count, tiles, Dbuf, wc, SLAB);
                     __syncthreads();
                 }
-                for (int64_t base = 0; base < total; base += kWave) {
-                    const int64_t idx = base + lane;
-                    int lo = 0, r = 0;
-                    if (idx < total) locate(idx, lo, r);
-                    if constexpr (QCAP == 0) {
+                if constexpr (QCAP == 0) {
+                    // phase 1 for every window of the batch first: the columns
+                    // that take the x complement need the last row's
+                    for (int64_t base = 0; base < total; base += kWave) {
+                        const int64_t idx = base + lane;
                         if (idx < total) {
+                            int lo = 0, r = 0;
+                            locate(idx, lo, r);
                             const Tile t = tiles[lo];
                             const CTet& S = slots[t_slot[lo]];
                             const int wb = t.tb + t.hb;
@@ -1433,8 +1453,13 @@ __global__ __launch_bounds__(kWave, ((SLAB ? CAP / 2 : CAP) <= 1408 ? 3 : 2)) vo
                             ++n_col;
                             if constexpr (WORK) n_colcell += (unsigned long long)t.tl;
                         }
-                        __syncthreads();
                     }
+                    __syncthreads();
+                }
+                for (int64_t base = 0; base < total; base += kWave) {
+                    const int64_t idx = base + lane;
+                    int lo = 0, r = 0;
+                    if (idx < total) locate(idx, lo, r);
                     // Phase 2: the cells (i, j, l) of this lane's column, l
                     // walking the tile's levels; halo columns have no cells.
                     if (idx < total) {
