@@ -65,6 +65,22 @@ __device__ __forceinline__ int wrap_cell(int x, int n) { return x >= n ? x - n :
 // 1 / (1 + e^-z) with the hardware reciprocal (1 ulp; 0 when e^-z overflows).
 __device__ __forceinline__ float sigmoid(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 
+// The deposit kernel runs the network on pre-activations scaled by -log2(e):
+// with y = -log2(e) z, 2^y = e^-z, so the sigmoid needs no multiply, and the
+// stored activation y * sigmoid(z) = -log2(e) silu(z) feeds the next layer
+// unscaled (its bias scaled by -log2(e) gives that layer's y).  The output
+// layer with negated weights and its bias times log2(e) then yields log2(e)
+// times the logits, so the softmax takes powers of 2.
+constexpr float kNegLog2e = -1.4426950408889634f;
+constexpr float kLog2e = 1.4426950408889634f;
+
+__device__ __forceinline__ float sigmoid_pow2(float y) { return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(y)); }
+
+// q = n / d for 0 <= n < 2^21 from the hardware reciprocal (relative error
+// up to 2^-23): (n + 1/2) * inv_d stays within (q, q + 1) because its error,
+// under (n + 1/2) * 1.8e-7 / d, is below 1/(2d).
+__device__ __forceinline__ int quot_small(int n, float inv_d) { return (int)(((float)n + 0.5f) * inv_d); }
+
 // Weight fragments of the A operand and bias columns, held per wave.
 // Lane l holds row (l & 15) of a 16-row tile, k = 8 (l >> 4) + 0..7.
 struct Net {
@@ -75,7 +91,7 @@ struct Net {
     const float* w;    // the packed parameters (biases are read from here, cached)
 };
 
-__device__ __forceinline__ void load_net(const float* __restrict__ w, Net& N)
+__device__ __forceinline__ void load_net(const float* __restrict__ w, Net& N, bool neg_out = false)
 {
     const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
 #pragma unroll
@@ -101,7 +117,8 @@ __device__ __forceinline__ void load_net(const float* __restrict__ w, Net& N)
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int k = ks * 32 + 8 * g + e;
-            N.w4[ks][e] = to_bf16(r < kOut ? w[oW4 + r * kH + k] : 0.0f);
+            const float v = r < kOut ? w[oW4 + r * kH + k] : 0.0f;
+            N.w4[ks][e] = to_bf16(neg_out ? -v : v);
         }
     N.w = w;
 }
@@ -184,7 +201,9 @@ __device__ __forceinline__ void xor_cells(float (&p)[kOut], int r)
 // One hidden layer over the wave's 64 tetrahedra: out[t][u] = silu(W in[t] + b),
 // optionally sp[t][u] = silu'(z).  `in` and `out` may be the same buffer (each
 // 16-tet tile is read completely before it is written).
-template <int KS, int IN_STRIDE>
+// With POW2 the layer works on y = -log2(e) z (bias scaled here, the input
+// already scaled) and writes y * sigmoid(z); sp must then be null.
+template <int KS, int IN_STRIDE, bool POW2 = false>
 __device__ __forceinline__ void hidden_layer(const __bf16* in, __bf16* out, __bf16* sp,
                                              const bf16x8 (&w)[4][KS], const float* __restrict__ bias)
 {
@@ -193,7 +212,7 @@ __device__ __forceinline__ void hidden_layer(const __bf16* in, __bf16* out, __bf
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) b[mt][i] = bias[mt * 16 + 4 * g + i];
+        for (int i = 0; i < 4; ++i) b[mt][i] = POW2 ? kNegLog2e * bias[mt * 16 + 4 * g + i] : bias[mt * 16 + 4 * g + i];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
         const int t = nt * 16 + col;
@@ -212,15 +231,18 @@ __device__ __forceinline__ void hidden_layer(const __bf16* in, __bf16* out, __bf
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const float z = acc[mt][i];
-                const float s = sigmoid(z);
+                const float s = POW2 ? sigmoid_pow2(z) : sigmoid(z);
                 const int u = mt * 16 + 4 * g + i;
                 out[t * kHS + u] = to_bf16(z * s);
-                if (sp) sp[t * kHS + u] = to_bf16(s * (1.0f + z * (1.0f - s)));
+                if (!POW2 && sp) sp[t * kHS + u] = to_bf16(s * (1.0f + z * (1.0f - s)));
             }
     }
 }
 
 // Output layer: logits lg[t][c] (float, row stride 8) for the wave's 64 tets.
+// With POW2 (negated output weights, base-2 activations) the logits come out
+// multiplied by log2(e).
+template <bool POW2 = false>
 __device__ __forceinline__ void output_layer(const __bf16* h3, float* lg, const Net& N)
 {
     const int lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
@@ -229,7 +251,7 @@ __device__ __forceinline__ void output_layer(const __bf16* h3, float* lg, const 
         const int t = nt * 16 + col;
         f32x4 acc;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i] = 4 * g + i < kOut ? N.w[oB4 + 4 * g + i] : 0.0f;
+        for (int i = 0; i < 4; ++i) acc[i] = 4 * g + i < kOut ? (POW2 ? kLog2e : 1.0f) * N.w[oB4 + 4 * g + i] : 0.0f;
         acc = mfma(N.w4[0], ld8(h3 + t * kHS + 8 * g), acc);
         acc = mfma(N.w4[1], ld8(h3 + t * kHS + 32 + 8 * g), acc);
         if (g < 2) *reinterpret_cast<f32x4*>(lg + t * kOut + 4 * g) = acc;
@@ -839,7 +861,7 @@ __global__ __launch_bounds__(64, 2) void surrogate_deposit_kernel(UniformArgs P,
     __shared__ __attribute__((aligned(16))) __bf16 hb[64 * kHS];
     __shared__ __attribute__((aligned(16))) float lg[64 * kOut];
     Net N;
-    load_net(P.surrogate, N);
+    load_net(P.surrogate, N, true);
     OutT* out = reinterpret_cast<OutT*>(P.out);
     const int lane = threadIdx.x;
     int head = 0, qn = 0;
@@ -852,13 +874,14 @@ __global__ __launch_bounds__(64, 2) void surrogate_deposit_kernel(UniformArgs P,
     // Lagrangian cubes and share most of their cells).  A batch whose union
     // is larger than the buffer adds straight to the grid.
     constexpr int kAcc = (int)(sizeof(hb) / (sizeof(OutT)));  // OutT entries in the bytes of hb
+    static_assert(kAcc < (1 << 21), "flush quotients");
     OutT* acc = reinterpret_cast<OutT*>(hb);
     auto run = [&](int n) {
         if (lane < n) {
             const int slot = (head + lane) & (kRing - 1);
             float x[kIn];
 #pragma unroll
-            for (int k = 0; k < kIn; ++k) x[k] = qx[slot * kIn + k];
+            for (int k = 0; k < kIn; ++k) x[k] = kNegLog2e * qx[slot * kIn + k];
             put_features(hb + lane * kHS, x);
         } else {
             float x[kIn];
@@ -867,10 +890,10 @@ __global__ __launch_bounds__(64, 2) void surrogate_deposit_kernel(UniformArgs P,
             put_features(hb + lane * kHS, x);
         }
         __syncthreads();
-        hidden_layer<1, kHS>(hb, hb, nullptr, N.w1, N.w + oB1);
-        hidden_layer<2, kHS>(hb, hb, nullptr, N.w2, N.w + oB2);
-        hidden_layer<2, kHS>(hb, hb, nullptr, N.w3, N.w + oB3);
-        output_layer(hb, lg, N);
+        hidden_layer<1, kHS, true>(hb, hb, nullptr, N.w1, N.w + oB1);
+        hidden_layer<2, kHS, true>(hb, hb, nullptr, N.w2, N.w + oB2);
+        hidden_layer<2, kHS, true>(hb, hb, nullptr, N.w3, N.w + oB3);
+        output_layer<true>(hb, lg, N);
         __syncthreads();
         // the union box, in cells relative to lane 0's block (minimum image)
         const int slot0 = head & (kRing - 1);
@@ -906,28 +929,35 @@ __global__ __launch_bounds__(64, 2) void surrogate_deposit_kernel(UniformArgs P,
         if (lane < n) {
             const int slot = (head + lane) & (kRing - 1);
             const int m = qm[slot * 4] & 0xFF, r = qm[slot * 4] >> 8;
-            float p[kOut];
-            masked_softmax(lg + lane * kOut, m, p);
-            xor_cells(p, r);
-            // renormalised in FP64; the last cell takes the residual so the
-            // deposits sum to m
-            double s = 0.0;
+            // softmax of the base-2 logits over the cells in m (the largest
+            // term is 1, so the sum is at least 1), in the tet's own cell order
+            float p[kOut], mx = -INFINITY, s = 0.0f;
 #pragma unroll
-            for (int c = 0; c < kOut; ++c) s += (double)p[c];
-            const double scale = P.m / s;
+            for (int c = 0; c < kOut; ++c)
+                if ((m >> c) & 1) mx = fmaxf(mx, lg[lane * kOut + c]);
+#pragma unroll
+            for (int c = 0; c < kOut; ++c) {
+                p[c] = ((m >> c) & 1) ? __builtin_amdgcn_exp2f(lg[lane * kOut + c] - mx) : 0.0f;
+                s += p[c];
+            }
+            xor_cells(p, r);
+            const float inv = __builtin_amdgcn_rcpf(s);
+            // FP64 shares; the last cell takes the residual so the deposits
+            // sum to m
             int last = 0;
 #pragma unroll
             for (int c = 0; c < kOut; ++c)
                 if ((m >> c) & 1) last = c;
+            const int ib = ((lo[0] - mn[0]) * E[1] + (lo[1] - mn[1])) * E[2] + (lo[2] - mn[2]);
             double given = 0.0;
+#pragma unroll
             for (int c = 0; c < kOut; ++c) {
                 if (!((m >> c) & 1)) continue;
-                const double d = c == last ? P.m - given : (double)p[c] * scale;
+                const double d = c == last ? P.m - given : (double)(p[c] * inv) * P.m;
                 given += d;
                 if (d == 0.0) continue;
                 if (tiled) {
-                    const int i = ((lo[0] - mn[0] + ((c >> 2) & 1)) * E[1] + (lo[1] - mn[1] + ((c >> 1) & 1))) *
-                                      E[2] + (lo[2] - mn[2] + (c & 1));
+                    const int i = ib + ((c >> 2) & 1) * E[1] * E[2] + ((c >> 1) & 1) * E[2] + (c & 1);
                     __hip_atomic_fetch_add(acc + i, (OutT)(d * P.out_scale), __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
                 } else {
@@ -942,19 +972,23 @@ __global__ __launch_bounds__(64, 2) void surrogate_deposit_kernel(UniformArgs P,
         }
         __syncthreads();
         if (tiled) {
-            // one global atomic per non-zero cell of the tile
+            // one global atomic per non-zero cell of the tile; ncell <= kAcc
+            // keeps the quotients exact, and the cell coordinates lie in
+            // [-nc/2, 2 nc) (lane 0's wrapped block plus offsets of at most
+            // nc/2 + E - 1), so one correction wraps them
+            const int E12 = E[1] * E[2];
+            const float rE2 = __builtin_amdgcn_rcpf((float)E[2]), rE12 = __builtin_amdgcn_rcpf((float)E12);
             for (int i = lane; i < ncell; i += 64) {
                 const OutT v = acc[i];
                 if (v == OutT(0)) continue;
-                const int i2 = i % E[2], i1 = (i / E[2]) % E[1], i0 = i / (E[1] * E[2]);
+                const int i0 = quot_small(i, rE12), rem = i - i0 * E12;
+                const int i1 = quot_small(rem, rE2), i2 = rem - i1 * E[2];
                 int g[3];
                 const int li[3] = {i0, i1, i2};
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    int x = qm[slot0 * 4 + 1 + a] + mn[a] + li[a];
-                    const int nca = P.nc[a];
-                    x = x % nca;
-                    g[a] = x < 0 ? x + nca : x;
+                    const int x = qm[slot0 * 4 + 1 + a] + mn[a] + li[a], nca = P.nc[a];
+                    g[a] = x < 0 ? x + nca : (x >= nca ? x - nca : x);
                 }
                 global_add(out + ((int64_t)g[0] * P.nc[1] + g[1]) * P.nc[2] + g[2], v);
             }
