@@ -460,6 +460,28 @@ psd_status psd_surrogate_backward(const float* params, const float* feat, const 
 psd_status psd_surrogate_adam(float* params, const float* grad, float* m, float* v, int64_t step,
                               float lr, float beta1, float beta2, float eps, void* stream);
 
+/*
+ * `steps` training steps in one launch (cooperative: its workgroups, one per
+ * 64-sample tile of a batch up to 256, are resident together and meet at
+ * grid-wide barriers).  Step s (0-based) takes the samples
+ * order[s*batch .. min((s+1)*batch, n) - 1] (DEVICE int64, n entries), forms
+ * their mean-loss gradient at the current params as psd_surrogate_backward
+ * does, then applies one Adam update as psd_surrogate_adam does, with step
+ * count step0 + s + 1 and learning rate lr[s] (DEVICE float[steps]).
+ * losses (DEVICE double[steps], or NULL) receives each step's mean loss;
+ * grad (DEVICE float[PSD_SURROGATE_PARAMS]) is scratch and ends zeroed.
+ * The result equals the per-step calls up to the order of the FP32 gradient
+ * sums across workgroups.  PSD_ERR_ARG: batch < 1, steps or n or step0
+ * negative, a step past the end of order, bad Adam hyper-parameters, a null
+ * pointer; PSD_ERR_HIP: the launch failed (e.g. the grid cannot be
+ * resident at once).  Asynchronous.
+ */
+psd_status psd_surrogate_train_steps(float* params, const float* feat, const double* frac,
+                                     const uint8_t* mask, const int64_t* order, int64_t n,
+                                     int64_t batch, int64_t steps, int64_t step0, const float* lr,
+                                     float beta1, float beta2, float eps, float* m, float* v,
+                                     float* grad, double* losses, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

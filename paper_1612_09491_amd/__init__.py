@@ -510,6 +510,11 @@ def _bind_surrogate(L):
     L.psd_surrogate_adam.restype = C.c_int
     L.psd_surrogate_adam.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                      C.c_float, C.c_float, C.c_float, C.c_float, C.c_void_p]
+    L.psd_surrogate_train_steps.restype = C.c_int
+    L.psd_surrogate_train_steps.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                            C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_int64,
+                                            C.c_void_p, C.c_float, C.c_float, C.c_float, C.c_void_p,
+                                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L._surrogate_bound = True
 
 
@@ -641,30 +646,78 @@ def surrogate_adam(params: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v:
            "psd_surrogate_adam")
 
 
+def surrogate_train_steps(params: torch.Tensor, feat: torch.Tensor, frac: torch.Tensor,
+                          mask: torch.Tensor, order: torch.Tensor, batch: int, lr: torch.Tensor,
+                          m: torch.Tensor, v: torch.Tensor, step0: int, grad: torch.Tensor,
+                          losses: torch.Tensor | None = None, beta1: float = 0.9,
+                          beta2: float = 0.999, eps: float = 1e-8, stream=None) -> None:
+    """len(lr) Adam steps in one launch: step s takes order[s*batch:(s+1)*batch], forms its
+    gradient at the current params and updates params, m, v in place with step count
+    step0 + s + 1 and rate lr[s]; losses[s] gets its mean loss.  grad is scratch."""
+    L = lib()
+    _bind_surrogate(L)
+    for t in (params, m, v, grad):
+        _check_params(t)
+    _cuda(feat, torch.float32, (12,), "feat")
+    _cuda(frac, torch.float64, (8,), "frac")
+    for t, dt, name in ((order, torch.int64, "order"), (lr, torch.float32, "lr"),
+                        (mask, torch.uint8, "mask")):
+        if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous CUDA {dt} tensor")
+    steps = int(lr.numel())
+    if losses is not None and (losses.dtype != torch.float64 or not losses.is_cuda or
+                               not losses.is_contiguous() or losses.numel() < steps):
+        raise ValueError(f"losses must be a contiguous CUDA float64 tensor of {steps} values")
+    _check(L.psd_surrogate_train_steps(params.data_ptr(), feat.data_ptr(), frac.data_ptr(),
+                                       mask.data_ptr(), order.data_ptr(), int(order.numel()),
+                                       int(batch), steps, int(step0), lr.data_ptr(), float(beta1),
+                                       float(beta2), float(eps), m.data_ptr(), v.data_ptr(),
+                                       grad.data_ptr(),
+                                       losses.data_ptr() if losses is not None else None,
+                                       _stream_handle(stream)),
+           "psd_surrogate_train_steps")
+
+
 def train_surrogate(params: torch.Tensor, feat: torch.Tensor, frac: torch.Tensor,
                     mask: torch.Tensor, order, batch: int = 4096, lr: float = 1e-3,
-                    lr_final: float | None = None, state=None, stream=None) -> dict:
+                    lr_final: float | None = None, state=None, stream=None,
+                    steps_per_launch: int = 256) -> dict:
     """Adam over the examples, batches taken in the given sample order (a host or device
     int64 array; the last batch may be shorter).  The learning rate decays geometrically to
-    lr_final over the run when given.  Every step is one backward and one Adam launch.
-    Returns the optimizer state (m, v, step) with the per-step losses (device float64)."""
+    lr_final over the run when given.  Up to steps_per_launch steps run in one launch
+    (psd_surrogate_train_steps); steps_per_launch=0 makes every step one backward and one
+    Adam launch.  Returns the optimizer state (m, v, step) with the per-step losses
+    (device float64)."""
     dev = feat.device
     if state is None:
         state = {"m": torch.zeros_like(params), "v": torch.zeros_like(params), "step": 0}
-    order_t = torch.as_tensor(order, dtype=torch.int64).to(dev)
+    order_t = torch.as_tensor(order, dtype=torch.int64).to(dev).contiguous()
     n = int(order_t.numel())
     steps = (n + batch - 1) // batch
     losses = torch.empty(steps, dtype=torch.float64, device=dev)
     grad = torch.empty_like(params)
     decay = (lr_final / lr) ** (1.0 / max(steps - 1, 1)) if lr_final else 1.0
+    rates = []
     rate = lr
-    for s in range(steps):
-        sl = order_t[s * batch:(s + 1) * batch]
-        surrogate_backward(params, feat, frac, mask, idx=sl, grad=grad, loss=losses[s:s + 1],
-                           stream=stream)
-        state["step"] += 1
-        surrogate_adam(params, grad, state["m"], state["v"], state["step"], rate, stream=stream)
+    for _ in range(steps):
+        rates.append(rate)
         rate *= decay
+    if steps_per_launch > 0:
+        rates_t = torch.tensor(rates, dtype=torch.float32).to(dev)
+        for s0 in range(0, steps, steps_per_launch):
+            k = min(steps_per_launch, steps - s0)
+            surrogate_train_steps(params, feat, frac, mask, order_t[s0 * batch:], batch,
+                                  rates_t[s0:s0 + k], state["m"], state["v"], state["step"], grad,
+                                  losses=losses[s0:s0 + k], stream=stream)
+            state["step"] += k
+    else:
+        for s in range(steps):
+            sl = order_t[s * batch:(s + 1) * batch]
+            surrogate_backward(params, feat, frac, mask, idx=sl, grad=grad, loss=losses[s:s + 1],
+                               stream=stream)
+            state["step"] += 1
+            surrogate_adam(params, grad, state["m"], state["v"], state["step"], rates[s],
+                           stream=stream)
     state["losses"] = losses
     return state
 

@@ -14,6 +14,11 @@ hipError_t launch_batched(const psd_box* boxes, int n, double* mass_sums, bool d
 size_t batched_ws_bytes(const psd_box* boxes, int n, bool ordered);
 hipError_t autotune_batched(const psd_box* boxes, int n, uint32_t flags, void* ws, size_t ws_bytes,
                             hipStream_t stream, const char* cache_path, Tuning& best, double& best_ms);
+// psd_surrogate.hip: `steps` backward + Adam steps in one cooperative launch.
+hipError_t launch_surrogate_train(float* w, const float* feat, const double* frac, const uint8_t* mask,
+                                  const int64_t* order, int64_t n, int64_t batch, int64_t steps,
+                                  int64_t step0, const float* lr, float beta1, float beta2, float eps,
+                                  float* m, float* v, float* grad, double* losses, hipStream_t stream);
 }  // namespace psd
 
 namespace {
@@ -549,6 +554,27 @@ psd_status psd_surrogate_adam(float* params, const float* grad, float* m, float*
     hipError_t e = psd::launch_surrogate_adam(params, grad, m, v, step, lr, beta1, beta2, eps,
                                               reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) return fail_hip(e, "surrogate_adam");
+    return PSD_OK;
+}
+
+psd_status psd_surrogate_train_steps(float* params, const float* feat, const double* frac,
+                                     const uint8_t* mask, const int64_t* order, int64_t n,
+                                     int64_t batch, int64_t steps, int64_t step0, const float* lr,
+                                     float beta1, float beta2, float eps, float* m, float* v,
+                                     float* grad, double* losses, void* stream)
+{
+    if (batch < 1 || steps < 0 || n < 0 || step0 < 0) return fail(PSD_ERR_ARG, "bad batch, step or sample count");
+    if (steps > 0 && (steps - 1) >= (n + batch - 1) / batch)
+        return fail(PSD_ERR_ARG, "more steps than batches in the sample order");
+    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return fail(PSD_ERR_ARG, "bad Adam hyper-parameters");
+    if (steps == 0) return PSD_OK;
+    if (!params || !feat || !frac || !mask || !order || !lr || !m || !v || !grad)
+        return fail(PSD_ERR_ARG, "null pointer");
+    hipError_t e = psd::launch_surrogate_train(params, feat, frac, mask, order, n, batch, steps, step0, lr,
+                                               beta1, beta2, eps, m, v, grad, losses,
+                                               reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail_hip(e, "surrogate_train_steps");
     return PSD_OK;
 }
 

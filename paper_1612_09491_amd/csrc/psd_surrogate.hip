@@ -18,6 +18,8 @@
 // registers for the life of the wave, and each lane of the epilogue writes 4
 // consecutive units of one tetrahedron.
 
+#include <hip/hip_cooperative_groups.h>
+
 #include "psd_internal.h"
 
 namespace psd {
@@ -681,9 +683,10 @@ struct BackLds {
     __bf16 ga[64 * kHS], gb[64 * kHS];
 };
 
-__global__ __launch_bounds__(64) void backward_kernel(NetIO io)
+// One wave per workgroup; the workgroups share the batch's 64-sample tiles
+// (blockIdx.x, stepping by gridDim.x) and add into io.grad and io.loss.
+__device__ __forceinline__ void backward_pass(const NetIO& io, BackLds& L)
 {
-    __shared__ __attribute__((aligned(16))) BackLds L;
     Net N;
     load_net(io.w, N);
     const int lane = threadIdx.x;
@@ -825,6 +828,12 @@ __global__ __launch_bounds__(64) void backward_kernel(NetIO io)
     if (lane == 0 && io.loss) atomicAdd(io.loss, lsum / (double)io.n);
 }
 
+__global__ __launch_bounds__(64) void backward_kernel(NetIO io)
+{
+    __shared__ __attribute__((aligned(16))) BackLds L;
+    backward_pass(io, L);
+}
+
 template <typename T>
 __global__ void fill_kernel(T* p, int64_t n, T v)
 {
@@ -833,17 +842,78 @@ __global__ void fill_kernel(T* p, int64_t n, T v)
         p[i] = v;
 }
 
-__global__ void adam_kernel(float* w, const float* g, float* m, float* v, int64_t n, float lr,
-                            float b1, float b2, float eps, float c1, float c2)
+// Adam (Kingma & Ba) for parameter i: moments from gradient g[i], update
+// with the bias corrections c1 = 1 - b1^t, c2 = 1 - b2^t.
+__device__ __forceinline__ void adam_update(float* w, float gi, float* m, float* v, int64_t i, float lr,
+                                            float b1, float b2, float eps, float c1, float c2)
 {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float gi = g[i];
     const float mi = b1 * m[i] + (1.0f - b1) * gi;
     const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
     m[i] = mi;
     v[i] = vi;
     w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void adam_kernel(float* w, const float* g, float* m, float* v, int64_t n, float lr,
+                            float b1, float b2, float eps, float c1, float c2)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    adam_update(w, g[i], m, v, i, lr, b1, b2, eps, c1, c2);
+}
+
+// Several training steps in one cooperative launch: per step, the batch's
+// gradient (every workgroup adds its tiles), a grid barrier, Adam over the
+// parameters with the gradient cleared behind it, a grid barrier.  Every
+// workgroup runs the same steps, so every barrier is reached by all.
+struct TrainArgs {
+    float* w;
+    const float* feat;
+    const double* frac;
+    const uint8_t* mask;
+    const int64_t* order;  // sample order; step s takes order[s * batch ..]
+    int64_t n;             // entries of order
+    int64_t batch;
+    int64_t steps;
+    int64_t step0;         // Adam updates done before this launch
+    const float* lr;       // [steps]
+    float b1, b2, eps;
+    float* m;
+    float* v;
+    float* grad;           // [kNParams], scratch: cleared here, cleared again at the end
+    double* losses;        // [steps] or null
+};
+
+__global__ __launch_bounds__(64) void train_kernel(TrainArgs A)
+{
+    __shared__ __attribute__((aligned(16))) BackLds L;
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    const int64_t gt = (int64_t)blockIdx.x * 64 + threadIdx.x, gs = (int64_t)gridDim.x * 64;
+    for (int64_t i = gt; i < kNParams; i += gs) A.grad[i] = 0.0f;
+    if (A.losses)
+        for (int64_t i = gt; i < A.steps; i += gs) A.losses[i] = 0.0;
+    grid.sync();
+    for (int64_t s = 0; s < A.steps; ++s) {
+        NetIO io = {};
+        io.w = A.w;
+        io.feat = A.feat;
+        io.frac = A.frac;
+        io.mask = A.mask;
+        io.idx = A.order + s * A.batch;
+        io.n = min(A.batch, A.n - s * A.batch);
+        io.grad = A.grad;
+        io.loss = A.losses ? A.losses + s : nullptr;
+        backward_pass(io, L);
+        grid.sync();
+        const double t = (double)(A.step0 + s + 1);
+        const float c1 = (float)(1.0 - pow((double)A.b1, t)), c2 = (float)(1.0 - pow((double)A.b2, t));
+        const float lr = A.lr[s];
+        for (int64_t i = gt; i < kNParams; i += gs) {
+            adam_update(A.w, A.grad[i], A.m, A.v, i, lr, A.b1, A.b2, A.eps, c1, c2);
+            A.grad[i] = 0.0f;
+        }
+        grid.sync();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1125,6 +1195,10 @@ static int net_grid(int64_t n)
     return (int)(tiles < cap ? (tiles > 0 ? tiles : 1) : cap);
 }
 
+// Workgroups of a training launch: one per 64-sample tile of a batch, at most
+// 256 (the batch's tiles are shared out when there are more).
+static int train_grid(int64_t batch) { return (int)((batch + 63) / 64 < 256 ? (batch + 63) / 64 : 256); }
+
 hipError_t launch_exact_fractions(const float* tets, double* frac, int64_t n, hipStream_t stream)
 {
     if (n == 0) return hipSuccess;
@@ -1177,6 +1251,35 @@ hipError_t launch_surrogate_adam(float* w, const float* grad, float* m, float* v
     hipLaunchKernelGGL(adam_kernel, dim3((kNParams + 255) / 256), dim3(256), 0, stream, w, grad, m, v,
                        (int64_t)kNParams, lr, beta1, beta2, eps, (float)c1, (float)c2);
     return hipGetLastError();
+}
+
+hipError_t launch_surrogate_train(float* w, const float* feat, const double* frac, const uint8_t* mask,
+                                  const int64_t* order, int64_t n, int64_t batch, int64_t steps,
+                                  int64_t step0, const float* lr, float beta1, float beta2, float eps,
+                                  float* m, float* v, float* grad, double* losses, hipStream_t stream)
+{
+    if (steps == 0) return hipSuccess;
+    TrainArgs A;
+    A.w = w;
+    A.feat = feat;
+    A.frac = frac;
+    A.mask = mask;
+    A.order = order;
+    A.n = n;
+    A.batch = batch;
+    A.steps = steps;
+    A.step0 = step0;
+    A.lr = lr;
+    A.b1 = beta1;
+    A.b2 = beta2;
+    A.eps = eps;
+    A.m = m;
+    A.v = v;
+    A.grad = grad;
+    A.losses = losses;
+    void* args[] = {&A};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(train_kernel), dim3(train_grid(batch)),
+                                      dim3(64), args, 0, stream);
 }
 
 hipError_t launch_surrogate_deposit(const UniformArgs& P, bool fp64, unsigned long long* exact_mask,

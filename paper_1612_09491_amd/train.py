@@ -66,7 +66,7 @@ def collect_examples(n_examples: int, np_: int = 256, rms: float = 2.0, nc: int 
 
 
 def train(params: torch.Tensor, ex: dict, epochs: int, batch: int, lr: float, lr_final: float,
-          seed: int, log=print) -> dict:
+          seed: int, log=print, steps_per_launch: int = 256) -> dict:
     n = int(ex["mask"].numel())
     rng = np.random.default_rng(seed)
     state = None
@@ -79,7 +79,7 @@ def train(params: torch.Tensor, ex: dict, epochs: int, batch: int, lr: float, lr
         rate = lr * decay ** (e * steps_per_epoch)
         state = psd.train_surrogate(params, ex["feat"], ex["frac"], ex["mask"], order, batch=batch,
                                     lr=rate, lr_final=rate * decay ** (steps_per_epoch - 1),
-                                    state=state)
+                                    state=state, steps_per_launch=steps_per_launch)
         mean_loss = float(state["losses"].mean().item())
         history.append(mean_loss)
         log(f"epoch {e}: mean loss {mean_loss:.5f} ({time.perf_counter() - t0:.1f} s)")
@@ -97,6 +97,9 @@ def main(argv=None) -> int:
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--lr-final", type=float, default=2e-5)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--steps-per-launch", type=int, default=256,
+                    help="Adam steps per cooperative launch (0: one backward and one Adam "
+                         "launch per step)")
     args = ap.parse_args(argv)
 
     def log(msg):
@@ -106,10 +109,12 @@ def main(argv=None) -> int:
     ex = collect_examples(args.examples, log=log)
     t_ex = time.perf_counter() - t0
     params = torch.from_numpy(initial_parameters(args.seed)).to("cuda:0")
-    rec = train(params, ex, args.epochs, args.batch, args.lr, args.lr_final, args.seed + 1, log=log)
+    rec = train(params, ex, args.epochs, args.batch, args.lr, args.lr_final, args.seed + 1, log=log,
+                steps_per_launch=args.steps_per_launch)
     w = params.cpu().numpy()
     np.save(args.out, w)
     rec.update({"examples": int(ex["mask"].numel()), "epochs": args.epochs, "batch": args.batch,
+                "steps_per_launch": args.steps_per_launch,
                 "lr": args.lr, "lr_final": args.lr_final, "init_seed": args.seed,
                 "example_seconds": t_ex, "train_boxes": "zeldovich(256, rms 2.0) -> 64^3, "
                 f"seeds {TRAIN_SEED0}..{TRAIN_SEED0 + 3}"})

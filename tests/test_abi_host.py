@@ -177,3 +177,23 @@ def test_slab_flag_combinations(psd):
         with pytest.raises(psd.PsdError) as e:
             psd.uniform_workspace_size((8, 8, 8), 16, flags=psd.PSD_METHOD_SLAB | bad)
         assert e.value.code == psd.PSD_ERR_UNSUPPORTED
+
+
+def test_train_steps_rejects_bad_arguments_before_launch(psd):
+    L = psd.lib()
+    psd._bind_surrogate(L)
+    f = C.c_void_p(0x1000)  # never dereferenced: checks fail first
+
+    def call(n=1000, batch=256, steps=4, step0=0, b1=0.9, b2=0.999, eps=1e-8, ptr=f):
+        return L.psd_surrogate_train_steps(ptr, f, f, f, f, n, batch, steps, step0, f, b1, b2,
+                                           eps, f, f, f, None, None)
+
+    assert call(steps=0) == psd.PSD_OK  # nothing to do, nothing launched
+    assert call(batch=0) == psd.PSD_ERR_ARG
+    assert call(steps=-1) == psd.PSD_ERR_ARG
+    assert call(step0=-1) == psd.PSD_ERR_ARG
+    assert call(steps=5) == psd.PSD_ERR_ARG  # 1000 samples hold 4 batches of 256
+    assert b"more steps" in L.psd_last_error_detail()
+    assert call(b1=1.0) == psd.PSD_ERR_ARG
+    assert call(eps=0.0) == psd.PSD_ERR_ARG
+    assert call(ptr=None) == psd.PSD_ERR_ARG

@@ -152,6 +152,39 @@ def test_backward_matches_reference(psd, orc):
         o += k
 
 
+@pytest.mark.parametrize("batch,n,per_launch,tol", [(64, 64 * 5, 5, (1e-6, 1e-8)),
+                                                    (256, 1000, 3, (1e-4, 2e-5))])
+def test_train_steps_match_per_step_calls(psd, orc, batch, n, per_launch, tol):
+    """Several steps per cooperative launch against one backward and one Adam launch per
+    step (each pinned to the FP64 reference above), from the same start and sample order.
+    One workgroup (batch 64) adds its gradient in a fixed order, so the two agree to FP32
+    rounding; with four the order of the gradient sums varies between runs.  The second
+    case has a ragged last batch and splits its 4 steps over two launches (3 + 1)."""
+    ex = _batch(orc)
+    rng = np.random.default_rng(31)
+    order = rng.integers(0, len(ex["tet"]), size=n).astype(np.int64)
+    feat, frac, mask = _dev(ex["feat"]), _dev(ex["frac"]), _dev(ex["mask"])
+    w0 = _theta(seed=13)
+    runs = []
+    for spl in (0, per_launch):
+        w = _dev(w0)
+        st = psd.train_surrogate(w, feat, frac, mask, order, batch=batch, lr=2e-3, lr_final=1e-3,
+                                 steps_per_launch=spl)
+        torch.cuda.synchronize()
+        runs.append((w.cpu().numpy(), st["m"].cpu().numpy(), st["v"].cpu().numpy(),
+                     st["losses"].cpu().numpy(), st["step"]))
+    (w1, m1, v1, l1, s1), (w2, m2, v2, l2, s2) = runs
+    rtol, atol = tol
+    steps = (n + batch - 1) // batch
+    assert s1 == s2 == steps and len(l1) == len(l2) == steps
+    print(f"train steps: max |dw| {np.abs(w1 - w2).max():.3e}, losses {l1} vs {l2}", flush=True)
+    assert np.all(np.isfinite(w2)) and np.abs(w2 - w0).max() > 1e-4  # the parameters moved
+    assert np.allclose(l2, l1, rtol=max(rtol, 1e-7), atol=0.0)
+    assert np.allclose(w2, w1, rtol=rtol, atol=atol)
+    assert np.allclose(m2, m1, rtol=rtol, atol=atol)
+    assert np.allclose(v2, v1, rtol=rtol, atol=atol * atol)
+
+
 def test_adam_matches_reference(psd):
     rng = np.random.default_rng(9)
     w = rng.normal(size=S.N_PARAMS).astype(np.float32)
